@@ -1,0 +1,89 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module holds random draws and data placement only: none of the PIC
+method's arithmetic.  It produces particle states as plain numpy arrays in the
+per-dimension (cell index, offset) form, plus random field arrays.
+
+* Positions: exactly ``ppc`` particles per cell, offsets uniform in [0,1)^D.
+* Momenta u = p/(m c): each component drawn from N(0, sigma^2), no mean removed.
+* Weights: a constant supplied by the caller.
+
+``round_f32`` snaps a state onto float32-representable values (offsets stay
+strictly below 1) so the FP32 path and the FP64 oracle start from the same
+numbers.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_plasma(n: tuple, dims: int, ppc: int, u_sigma: float, weight: float, seed: int,
+                   q: float = -1.0, m: float = 1.0, u_mean: tuple = (0.0, 0.0, 0.0)) -> dict:
+    """``ppc`` particles in every cell of an n[0] x n[1] x n[2] box (n[2] = 1 in 2D),
+    ordered cell by cell (x fastest), offsets uniform, momenta Gaussian."""
+    g = rng(seed)
+    ncell = int(n[0] * n[1] * n[2])
+    npart = ncell * ppc
+    lin = np.repeat(np.arange(ncell, dtype=np.int64), ppc)
+    cell = np.zeros((3, npart), np.int32)
+    cell[0] = lin % n[0]
+    cell[1] = (lin // n[0]) % n[1]
+    cell[2] = lin // (n[0] * n[1])
+    off = np.zeros((3, npart), np.float64)
+    off[:dims] = g.random((dims, npart))
+    u = g.normal(0.0, u_sigma, (3, npart)) if u_sigma > 0 else np.zeros((3, npart))
+    u = u + np.asarray(u_mean, np.float64)[:, None]
+    w = np.full(npart, weight, np.float64)
+    return {"q": float(q), "m": float(m), "cell": cell, "off": off, "u": np.ascontiguousarray(u), "w": w}
+
+
+def shuffle(sp: dict, seed: int) -> dict:
+    """Random permutation of the particles (order carries no physics)."""
+    perm = rng(seed).permutation(sp["w"].shape[0])
+    out = dict(sp)
+    for k in ("cell", "off", "u"):
+        out[k] = np.ascontiguousarray(sp[k][:, perm])
+    out["w"] = np.ascontiguousarray(sp["w"][perm])
+    return out
+
+
+def random_particles(n: tuple, dims: int, npart: int, u_sigma: float, weight_range: tuple, seed: int,
+                     q: float = -1.0, m: float = 1.0) -> dict:
+    """``npart`` particles at uniform random cells and offsets, random weights."""
+    g = rng(seed)
+    cell = np.zeros((3, npart), np.int32)
+    for d in range(dims):
+        cell[d] = g.integers(0, n[d], npart)
+    off = np.zeros((3, npart), np.float64)
+    off[:dims] = g.random((dims, npart))
+    u = np.ascontiguousarray(g.normal(0.0, u_sigma, (3, npart)))
+    w = g.uniform(weight_range[0], weight_range[1], npart)
+    return {"q": float(q), "m": float(m), "cell": cell, "off": off, "u": u, "w": w}
+
+
+def random_fields(ncells: int, scale: float, seed: int) -> dict:
+    """E and B with N(0, scale^2) entries, J zero; arrays (3, ncells)."""
+    g = rng(seed)
+    return {"E": g.normal(0.0, scale, (3, ncells)), "B": g.normal(0.0, scale, (3, ncells)),
+            "J": np.zeros((3, ncells))}
+
+
+def round_f32(sp: dict) -> dict:
+    """Snap offsets, momenta and weights to float32 values (kept as float64).
+    Offsets that would round up to 1.0 are set to the largest float32 below 1."""
+    out = dict(sp)
+    off = sp["off"].astype(np.float32)
+    off = np.where(off >= np.float32(1.0), np.nextafter(np.float32(1.0), np.float32(0.0)), off)
+    out["off"] = np.ascontiguousarray(off.astype(np.float64))
+    out["u"] = np.ascontiguousarray(sp["u"].astype(np.float32).astype(np.float64))
+    out["w"] = np.ascontiguousarray(sp["w"].astype(np.float32).astype(np.float64))
+    out["cell"] = np.ascontiguousarray(sp["cell"].copy())
+    return out
+
+
+def round_fields_f32(f: dict) -> dict:
+    return {k: np.ascontiguousarray(v.astype(np.float32).astype(np.float64)) for k, v in f.items()}

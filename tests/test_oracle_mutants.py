@@ -1,0 +1,71 @@
+"""The pins must catch plausible mistakes: each case below compiles a copy of
+the oracle with one planted mistake (on the CPU, in a temporary directory) and
+asserts that at least one pin fails against it."""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, original text, mutated text): each replaces the first occurrence
+MUTANTS = [
+    ("quadratic_centre", "if (a <= 0.5) return 0.75 - a * a;", "if (a <= 0.5) return 0.75 - a;"),
+    ("linear_shape", "return a < 1.0 ? 1.0 - a : 0.0;", "return a < 1.0 ? 1.0 - a * a : 0.0;"),
+    ("gather_stagger_Bx", "{0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}", "{0.5, 0.5, 0.5}, {0.5, 0.0, 0.5}"),
+    ("gather_stagger_sign", "((double)(-di) - STAG[c][0]) + off[0]", "((double)(-di) + STAG[c][0]) + off[0]"),
+    ("boris_s_factor", "double s[3] = {2.0 * t[0] / (1.0 + t2), 2.0 * t[1] / (1.0 + t2), 2.0 * t[2] / (1.0 + t2)};",
+     "double s[3] = {t[0] / (1.0 + t2), t[1] / (1.0 + t2), t[2] / (1.0 + t2)};"),
+    ("boris_cross_sign", "um[0] + (up[1] * s[2] - up[2] * s[1])", "um[0] + (up[2] * s[1] - up[1] * s[2])"),
+    ("boris_second_kick", "ux[p] = uplus[0] + h * E[0];", "ux[p] = uplus[0];"),
+    ("boris_gamma", "double t[3] = {h * B[0] / gm, h * B[1] / gm, h * B[2] / gm};",
+     "double t[3] = {h * B[0], h * B[1], h * B[2]};"),
+    ("move_nonrelativistic", "double disp = g->dt * (u[d] / gam) / g->dx[d];", "double disp = g->dt * u[d] / g->dx[d];"),
+    ("move_wrong_dx", "double disp = g->dt * (u[d] / gam) / g->dx[d];", "double disp = g->dt * (u[d] / gam) / g->dx[0];"),
+    ("esirkepov_half", "+ 0.5 * DS[1][j] * S0[2][k]", "+ DS[1][j] * S0[2][k]"),
+    ("esirkepov_third", "DS[1][j] * DS[2][k] / 3.0", "DS[1][j] * DS[2][k] / 2.0"),
+    ("esirkepov_sign", "double cx = -qw * g->dx[0] / g->dt, cy", "double cx = qw * g->dx[0] / g->dt, cy"),
+    ("esirkepov_new_cell", "double xi1 = (2.0 + (double)dcell[(int64_t)d * np + p]) + o1[d][p];",
+     "double xi1 = 2.0 + o1[d][p];"),
+    ("esirkepov_2d_jz_velocity", "qw * vz * Wz[j][i]", "qw * uz[p] * Wz[j][i]"),
+    ("esirkepov_2d_jz_weight", "Wz[j][i] = S0[0][i] * S0[1][j] + 0.5 * DS[0][i] * S0[1][j]",
+     "Wz[j][i] = S0[0][i] * S0[1][j] + DS[0][i] * S0[1][j]"),
+    ("yee_b_sign", "Bx[o] -= c * (dEz_dy - dEy_dz);", "Bx[o] -= c * (dEz_dy + dEy_dz);"),
+    ("yee_b_dz", "double dEy_dz = three ? (Ey[lin(g, i, j, k + 1)] - Ey[o]) / g->dx[2] : 0.0;",
+     "double dEy_dz = three ? (Ey[lin(g, i, j, k + 1)] - Ey[o]) / g->dx[1] : 0.0;"),
+    ("yee_e_current_sign", "Ex[o] += c * ((dBz_dy - dBy_dz) - Jx[o]);", "Ex[o] += c * ((dBz_dy - dBy_dz) + Jx[o]);"),
+    ("yee_e_forward_difference", "double dBz_dy = (Bz[o] - Bz[lin(g, i, j - 1, k)]) / g->dx[1];",
+     "double dBz_dy = (Bz[lin(g, i, j + 1, k)] - Bz[o]) / g->dx[1];"),
+    ("rho_volume", "+= q * w[p] / dV * (wx * wy * wz);", "+= q * w[p] * (wx * wy * wz);"),
+    ("div_stagger", "double d = (Fx[o] - Fx[lin(g, i - 1, j, k)]) / g->dx[0]",
+     "double d = (Fx[lin(g, i + 1, j, k)] - Fx[o]) / g->dx[0]"),
+]
+
+
+def _run_pins():
+    failed = []
+    for i, p in enumerate(pins.ALL_PINS):
+        try:
+            p()
+        except AssertionError:
+            failed.append(i)
+        except Exception:  # a crash or a NaN comparison counts as caught
+            failed.append(i)
+    return failed
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_mutant(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"mutation target for {name} not found"
+    mutated = src.replace(old, new, 1)
+    c = tmp_path / "oracle_mut.c"
+    c.write_text(mutated)
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", *oracle.CFLAGS, "-o", str(so), str(c), "-lm"])
+    with oracle.use_library(str(so)):
+        failed = _run_pins()
+    assert failed, f"no pin caught mutant {name}"
