@@ -1,0 +1,202 @@
+/*
+ * pic.h - C ABI of the MI355X (gfx950) hot path of an explicit electromagnetic
+ * particle-in-cell step.
+ *
+ * What a step computes (paper Sec. 2): macro-particles sample the Vlasov
+ * equation (eq. 1) through a compact shape g (eq. 2); each step
+ *   1. gathers E and B at every particle as the g-weighted average of the grid
+ *      fields,
+ *   2. advances the momentum with the relativistic Boris rotation and the
+ *      position with leap-frog (eq. 3),
+ *   3. deposits the current (eq. 4) in the charge-conserving form of
+ *      Esirkepov (Comput. Phys. Commun. 135 (2001) 144), so the discrete
+ *      continuity equation holds exactly,
+ *   4. advances E and B with the two curl equations on the Yee lattice (FDTD).
+ *
+ * Units (Sec. 2, "suitably normalised"): c = eps0 = 1, charge in units of e,
+ * mass in units of m_e, u = p/(m c), v = u/gamma; dE/dt = curl B - J,
+ * dB/dt = -curl E.
+ *
+ * Grid and staggering.  The box has n[0] x n[1] x n[2] cells (n[2] = 1 in 2D),
+ * periodic in every dimension.  Every field component is an array of
+ * n[0]*n[1]*n[2] values, x fastest (index i + n0*(j + n1*k)); the entry at
+ * (i,j,k) sits at the component's Yee position:
+ *   Ex (i+1/2, j, k)     Ey (i, j+1/2, k)     Ez (i, j, k+1/2)
+ *   Bx (i, j+1/2, k+1/2) By (i+1/2, j, k+1/2) Bz (i+1/2, j+1/2, k)
+ *   Jx, Jy, Jz at the E positions; charge density on nodes (i, j, k).
+ * In 2D (dims == 2) nothing varies along z and the k index is dropped.
+ * Time levels: positions, E and B at step n; momenta at n-1/2 -> n+1/2;
+ * J at n+1/2 (B is advanced in two half steps so that B^n exists).
+ *
+ * Particles (Sec. 3.3: seven values per particle, positions, momenta, weight,
+ * held as separate arrays).  A position is a packed integer cell index plus
+ * an offset in [0,1) per dimension: x_d = (cell_d + off_d) * dx_d.  The packed
+ * cell is  ix | iy << bx | iz << (bx + by)  with b_d = ceil(log2(n_d)) bits
+ * (pic_cell_bits returns them).  Offsets, momenta and weights are float
+ * (PIC_FP32) or double (PIC_FP64); so are the fields.  Shapes are B-splines
+ * of order 1 (linear) or 2 (quadratic) in cell units.
+ *
+ * Ownership and streams.  The caller owns every device array (fields,
+ * particles, the workspace) and the host structs; the library only borrows
+ * pointers for the work it enqueues and never frees them.  Every call
+ * enqueues on the given hipStream_t (NULL = default stream) and returns
+ * without synchronising, except pic_diagnostics, pic_check and
+ * pic_get_timing, which synchronise the stream.  A context is not
+ * thread-safe; separate contexts are.
+ *
+ * Errors.  Every call returns a pic_status and never throws.  Argument errors
+ * are found on the host before anything is launched.  HIP errors map to
+ * PIC_EHIP with the text kept for pic_last_error.  Conditions found on the
+ * device (a particle displaced by a full cell or more in one step, or a
+ * non-finite position) set a sticky flag in the workspace that the next
+ * pic_check or pic_diagnostics reports; such a particle is left where it was
+ * and deposits nothing.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+typedef enum {
+    PIC_OK = 0,
+    PIC_EINVAL = -1, /* bad argument: null pointer, size mismatch, unsupported option */
+    PIC_ECFL = -2,   /* dt at or above the Yee limit 1/sqrt(sum_d 1/dx_d^2) */
+    PIC_EHIP = -3,   /* HIP runtime error (text in pic_last_error) */
+    PIC_ENOMEM = -4, /* no workspace set, or the one set is too small */
+    PIC_ECROSS = -5, /* device flag: a particle moved a full cell or more, or became non-finite */
+    PIC_ENAN = -6,   /* device flag: a non-finite energy in the diagnostics */
+    PIC_ESTATE = -7  /* call out of order, e.g. pic_deposit not preceded by pic_gather_push */
+} pic_status;
+
+enum { PIC_FP32 = 0, PIC_FP64 = 1 };
+
+/* The "grid" element of the paper's object model (Sec. 3.2). */
+typedef struct {
+    int32_t dims;          /* 2 (2D3V) or 3 (3D3V) */
+    int32_t n[3];          /* cells per dimension, each >= 4; n[2] must be 1 when dims == 2 */
+    double dx[3];          /* cell sizes (> 0); dx[2] ignored in 2D */
+    double dt;             /* time step, 0 < dt < 1/sqrt(sum_d 1/dx_d^2), else PIC_ECFL */
+    int32_t shape_order;   /* 1 = linear (cloud in cell), 2 = quadratic */
+    int32_t precision;     /* PIC_FP32 or PIC_FP64 */
+    int32_t tile[3];       /* cells per sort tile; each divides n[d]; tile[2] = 1 in 2D */
+    int32_t slack;         /* guard cells beyond the shape's reach in the LDS tile (0..4):
+                              a particle may drift this far out of its tile between sorts
+                              and still take the on-chip path */
+    int32_t sort_every;    /* pic_step re-sorts every this many steps (>= 1) */
+    int64_t max_particles; /* the largest np of any species used with this context */
+} pic_params;
+
+/* The "em-field" element (Sec. 3.2): E, B and J as nine device arrays of
+ * n[0]*n[1]*n[2] float or double values each (layout above). */
+typedef struct {
+    void *E[3];
+    void *B[3];
+    void *J[3];
+} pic_fields;
+
+/* The "particle" element (Sec. 3.2) for one species (charge q, mass m). */
+typedef struct {
+    int64_t np;         /* particles in use, 0 <= np <= max_particles */
+    double q, m;        /* charge (units of e) and mass (units of m_e), m > 0 */
+    int32_t *cell;      /* packed cell index per particle */
+    void *off[3];       /* offsets in [0,1) per dimension (off[2] unused in 2D) */
+    void *u[3];         /* momentum p/(m c), three components */
+    void *w;            /* macro-particle weight (physical particles per macro-particle) */
+    /* A second set of arrays of the same sizes.  pic_sort writes the sorted
+     * particles into it and then swaps the two sets in this struct, so after a
+     * sort the pointers above name what were the *_alt arrays. */
+    int32_t *cell_alt;
+    void *off_alt[3];
+    void *u_alt[3];
+    void *w_alt;
+    int32_t *tile_start; /* device array of pic_num_tiles()+1 entries, written by pic_sort:
+                            particles of tile t are [tile_start[t], tile_start[t+1]) */
+    int32_t sorted;      /* set to 1 by pic_sort; the caller sets 0 after it edits particles */
+} pic_species;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Validate the parameters and create a context (host memory only).
+ * Returns PIC_EINVAL / PIC_ECFL without creating anything on bad input. */
+pic_status pic_init(const pic_params *params, pic_ctx **out);
+void pic_destroy(pic_ctx *ctx);
+
+/* Bytes of device workspace the context needs (saved old positions, sort keys,
+ * tile counts, diagnostics partials and charge grids).  The caller allocates it
+ * (>= 256-byte aligned) and hands it over; it must stay valid while the context
+ * is used.  PIC_ENOMEM if bytes is smaller than required. */
+size_t pic_workspace_bytes(const pic_ctx *ctx);
+pic_status pic_set_workspace(pic_ctx *ctx, void *device_ptr, size_t bytes);
+
+int64_t pic_num_tiles(const pic_ctx *ctx);
+void pic_cell_bits(const pic_ctx *ctx, int32_t bits[3]);
+/* Bytes of LDS one workgroup of the fused kernel uses (fields + current tile). */
+size_t pic_tile_lds_bytes(const pic_ctx *ctx);
+
+/* Steps 1-2 (Sec. 2, eq. 3): gather E^n, B^n at x^n, Boris rotation
+ * u^{n-1/2} -> u^{n+1/2}, leap-frog x^n -> x^{n+1}.  x^n is kept in the
+ * workspace for the pic_deposit call that must follow for the same species. */
+pic_status pic_gather_push(pic_ctx *ctx, pic_species *sp, const pic_fields *f, void *stream);
+
+/* Step 3 (eq. 4 with continuity enforced): J += Esirkepov current of the move
+ * recorded by the preceding pic_gather_push of this species.  J is not
+ * cleared first (pic_zero_current does that).  PIC_ESTATE if no matching
+ * pic_gather_push preceded it. */
+pic_status pic_deposit(pic_ctx *ctx, const pic_species *sp, pic_fields *f, void *stream);
+pic_status pic_zero_current(pic_ctx *ctx, pic_fields *f, void *stream);
+
+/* Step 4 (Sec. 2, curl equations, Yee FDTD): B^{n+1/2} = B^n - dt/2 curl E^n,
+ * E^{n+1} = E^n + dt (curl B^{n+1/2} - J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}. */
+pic_status pic_yee_step(pic_ctx *ctx, pic_fields *f, void *stream);
+
+/* Bin one species by tile (counting sort by tile index, x-fastest tile
+ * numbering); order inside a tile is unspecified.  Writes tile_start, swaps
+ * the array sets (see pic_species) and sets sorted = 1. */
+pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
+
+/* nsteps whole steps for nspecies species: sort when needed (unsorted species,
+ * or every sort_every steps), clear J, fused gather + push + deposit per tile
+ * with fields and current staged on chip, then the Yee update. */
+pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields *f, int32_t nsteps, void *stream);
+
+/* FP64 diagnostics of the current state, accumulated in double on the device,
+ * synchronising.  out[0..7] =
+ *   U_E = 1/2 sum E^2 dV,  U_B = 1/2 sum B^2 dV,  K = sum w m (gamma - 1),
+ *   Q = sum q w,  max |rho|,  max |div E - rho|  (the uniform background is
+ *   not included), max |G - G_prev| with G = div E - rho from the previous
+ *   pic_diagnostics call (NaN if none), and the continuity residual
+ *   max |(rho - rho_prev)/dt + div J| when exactly one step separates this
+ *   call from the previous one (NaN otherwise). */
+#define PIC_NDIAG 8
+pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
+                           double *out_host, void *stream);
+
+/* Synchronise and report sticky device flags (PIC_ECROSS), then clear them. */
+pic_status pic_check(pic_ctx *ctx, void *stream);
+
+/* Per-phase timing with HIP events on the call's stream: when on, pic_step
+ * records an event pair around every launch; pic_get_timing synchronises and
+ * returns the summed milliseconds and launch counts of each phase, in the
+ * order sort, zero_current, push_deposit, yee; then resets them. */
+#define PIC_NPHASE 4
+pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
+pic_status pic_get_timing(pic_ctx *ctx, double *ms, int64_t *launches, int32_t nphase);
+
+/* Step counter (pic_step and pic_yee_step each count one per step). */
+int64_t pic_step_count(const pic_ctx *ctx);
+
+const char *pic_last_error(const pic_ctx *ctx);
+const char *pic_status_string(pic_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,413 @@
+// Host side of the C ABI declared in pic.h: parameter validation, workspace
+// layout, phase ordering, per-phase timing and error reporting.  No call
+// allocates device memory; every launch goes on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "pic_internal.h"
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+int ceil_log2(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+pic_status fail(pic_ctx *c, pic_status s, const char *msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+pic_status hip_fail(pic_ctx *c, hipError_t e, const char *where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return PIC_EHIP;
+}
+
+bool fields_ok(const pic_fields *f) {
+  if (!f) return false;
+  for (int d = 0; d < 3; ++d)
+    if (!f->E[d] || !f->B[d] || !f->J[d]) return false;
+  return true;
+}
+
+bool species_ok(const pic_ctx *c, const pic_species *s, bool need_alt) {
+  if (!s) return false;
+  if (s->np < 0 || s->np > c->p.max_particles) return false;
+  if (!(s->m > 0.0) || !std::isfinite(s->q)) return false;
+  if (s->np == 0) return true;
+  if (!s->cell || !s->w) return false;
+  for (int d = 0; d < c->p.dims; ++d)
+    if (!s->off[d]) return false;
+  for (int d = 0; d < 3; ++d)
+    if (!s->u[d]) return false;
+  if (need_alt) {
+    if (!s->cell_alt || !s->w_alt || !s->tile_start) return false;
+    for (int d = 0; d < c->p.dims; ++d)
+      if (!s->off_alt[d]) return false;
+    for (int d = 0; d < 3; ++d)
+      if (!s->u_alt[d]) return false;
+  }
+  return true;
+}
+
+// Record the start of a timed phase (no-op unless timing is on).
+struct PhaseTimer {
+  pic_ctx *c;
+  hipStream_t s;
+  int phase;
+  hipEvent_t a = nullptr;
+  PhaseTimer(pic_ctx *c_, hipStream_t s_, int ph) : c(c_), s(s_), phase(ph) {
+    if (!c->timing) return;
+    a = take();
+    hipEventRecord(a, s);
+  }
+  hipEvent_t take() {
+    hipEvent_t e;
+    if (!c->spare.empty()) {
+      e = c->spare.back();
+      c->spare.pop_back();
+    } else {
+      hipEventCreate(&e);
+    }
+    return e;
+  }
+  ~PhaseTimer() {
+    if (!c->timing || !a) return;
+    hipEvent_t b = take();
+    hipEventRecord(b, s);
+    c->events.push_back({phase, a, b});
+  }
+};
+
+void collect_timing(pic_ctx *c) {
+  for (auto &ev : c->events) {
+    hipEventSynchronize(ev.b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ev.a, ev.b);
+    c->ms[ev.phase] += ms;
+    c->launches[ev.phase] += 1;
+    c->spare.push_back(ev.a);
+    c->spare.push_back(ev.b);
+  }
+  c->events.clear();
+}
+
+pic_status check_ws(pic_ctx *c) {
+  if (!c->wsptr) return fail(c, PIC_ENOMEM, "no workspace set (pic_set_workspace)");
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_status_string(pic_status s) {
+  switch (s) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ECFL: return "time step at or above the Yee stability limit";
+    case PIC_EHIP: return "HIP runtime error";
+    case PIC_ENOMEM: return "workspace missing or too small";
+    case PIC_ECROSS: return "a particle moved a full cell or more in one step, or became non-finite";
+    case PIC_ENAN: return "non-finite diagnostic";
+    case PIC_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+pic_status pic_init(const pic_params *p, pic_ctx **out) {
+  if (!p || !out) return PIC_EINVAL;
+  *out = nullptr;
+  if (p->dims != 2 && p->dims != 3) return PIC_EINVAL;
+  if (p->shape_order != 1 && p->shape_order != 2) return PIC_EINVAL;
+  if (p->precision != PIC_FP32 && p->precision != PIC_FP64) return PIC_EINVAL;
+  if (p->max_particles < 0 || p->max_particles > (int64_t(1) << 31) - 1) return PIC_EINVAL;
+  if (p->sort_every < 1 || p->slack < 0 || p->slack > 4) return PIC_EINVAL;
+  for (int d = 0; d < 3; ++d) {
+    const bool used = d < p->dims;
+    if (used) {
+      if (p->n[d] < 4 || !(p->dx[d] > 0.0) || !std::isfinite(p->dx[d])) return PIC_EINVAL;
+      if (p->tile[d] < 1 || p->n[d] % p->tile[d] != 0) return PIC_EINVAL;
+    } else {
+      if (p->n[d] != 1 || p->tile[d] != 1) return PIC_EINVAL;
+    }
+  }
+  int64_t ncells = 1;
+  int bits = 0;
+  for (int d = 0; d < p->dims; ++d) {
+    ncells *= p->n[d];
+    bits += ceil_log2(p->n[d]);
+  }
+  if (bits > 31) return PIC_EINVAL;
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return PIC_EINVAL;
+  double s = 0.0;
+  for (int d = 0; d < p->dims; ++d) s += 1.0 / (p->dx[d] * p->dx[d]);
+  if (p->dt >= 1.0 / std::sqrt(s)) return PIC_ECFL;
+
+  pic_ctx *c = new (std::nothrow) pic_ctx();
+  if (!c) return PIC_ENOMEM;
+  c->p = *p;
+  c->ncells = ncells;
+  c->ntiles = 1;
+  for (int d = 0; d < 3; ++d) {
+    c->n[d] = p->n[d];
+    c->bits[d] = d < p->dims ? ceil_log2(p->n[d]) : 0;
+    c->ntile[d] = p->n[d] / p->tile[d];
+    c->ntiles *= c->ntile[d];
+  }
+  c->elem = p->precision == PIC_FP64 ? 8 : 4;
+  // LDS tile geometry: the gather reaches [c-1, c+M] around the particle's
+  // cell, the Esirkepov window [c-M, c+M+1]; slack widens both on each side.
+  const int M = p->shape_order;
+  const int f_lo = 1, f_hi = M, j_lo = M, j_hi = M + 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d < p->dims) {
+      c->gf_lo[d] = f_lo + p->slack;
+      c->rf[d] = p->tile[d] + f_lo + f_hi + 2 * p->slack;
+      c->gj_lo[d] = j_lo + p->slack;
+      c->rj[d] = p->tile[d] + j_lo + j_hi + 2 * p->slack;
+    } else {
+      c->gf_lo[d] = c->gj_lo[d] = 0;
+      c->rf[d] = c->rj[d] = 1;
+    }
+  }
+  c->lds_bytes = (6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] +
+                  3 * static_cast<size_t>(c->rj[0]) * c->rj[1] * c->rj[2]) *
+                 c->elem;
+  if (c->lds_bytes > 160 * 1024) {
+    delete c;
+    return PIC_EINVAL;
+  }
+  // workspace layout
+  pic::Workspace &w = c->ws;
+  size_t off = 0;
+  const size_t mp = static_cast<size_t>(p->max_particles);
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  w.flags = take(64 * sizeof(int32_t));
+  w.save_cell = take(mp * 4);
+  w.save_off = take(3 * mp * c->elem);
+  w.sort_key = take(mp * 4);
+  w.sort_rank = take(mp * 4);
+  w.tile_count = take((static_cast<size_t>(c->ntiles) + 1) * 4);
+  w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
+  w.result = take(16 * 8);
+  w.rho = take(static_cast<size_t>(ncells) * 8);
+  w.rho_prev = take(static_cast<size_t>(ncells) * 8);
+  w.gauss_prev = take(static_cast<size_t>(ncells) * 8);
+  w.total = off;
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx *c) {
+  if (!c) return;
+  for (auto &ev : c->events) {
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  for (auto e : c->spare) hipEventDestroy(e);
+  delete c;
+}
+
+size_t pic_workspace_bytes(const pic_ctx *c) { return c ? c->ws.total : 0; }
+int64_t pic_num_tiles(const pic_ctx *c) { return c ? c->ntiles : 0; }
+size_t pic_tile_lds_bytes(const pic_ctx *c) { return c ? c->lds_bytes : 0; }
+int64_t pic_step_count(const pic_ctx *c) { return c ? c->step : 0; }
+
+void pic_cell_bits(const pic_ctx *c, int32_t bits[3]) {
+  if (!c || !bits) return;
+  for (int d = 0; d < 3; ++d) bits[d] = c->bits[d];
+}
+
+const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+pic_status pic_set_workspace(pic_ctx *c, void *ptr, size_t bytes) {
+  if (!c) return PIC_EINVAL;
+  if (!ptr) return fail(c, PIC_EINVAL, "workspace pointer is null");
+  if ((reinterpret_cast<uintptr_t>(ptr) & 255) != 0) return fail(c, PIC_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < c->ws.total) return fail(c, PIC_ENOMEM, "workspace smaller than pic_workspace_bytes()");
+  c->wsptr = static_cast<char *>(ptr);
+  c->wsbytes = bytes;
+  c->diag_step = -1;
+  c->pending_cell = nullptr;
+  hipError_t e = hipMemset(c->wsptr + c->ws.flags, 0, 64 * sizeof(int32_t));
+  if (e != hipSuccess) return hip_fail(c, e, "clearing workspace flags");
+  return PIC_OK;
+}
+
+pic_status pic_gather_push(pic_ctx *c, pic_species *sp, const pic_fields *f, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!species_ok(c, sp, false)) return fail(c, PIC_EINVAL, "bad species");
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  hipError_t e = pic::launch_gather_push(*c, *sp, *f, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "gather_push");
+  c->pending_cell = sp->cell;
+  c->pending_np = sp->np;
+  return PIC_OK;
+}
+
+pic_status pic_deposit(pic_ctx *c, const pic_species *sp, pic_fields *f, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!species_ok(c, sp, false)) return fail(c, PIC_EINVAL, "bad species");
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  if (c->pending_cell != sp->cell || c->pending_np != sp->np)
+    return fail(c, PIC_ESTATE, "pic_deposit must follow pic_gather_push of the same species");
+  hipError_t e = pic::launch_deposit(*c, *sp, *f, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "deposit");
+  c->pending_cell = nullptr;
+  return PIC_OK;
+}
+
+pic_status pic_zero_current(pic_ctx *c, pic_fields *f, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  for (int d = 0; d < 3; ++d) {
+    hipError_t e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(c, e, "zero_current");
+  }
+  return PIC_OK;
+}
+
+pic_status pic_yee_step(pic_ctx *c, pic_fields *f, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pic::launch_yee_b(*c, *f, 0.5, s);
+  if (e == hipSuccess) e = pic::launch_yee_e(*c, *f, s);
+  if (e == hipSuccess) e = pic::launch_yee_b(*c, *f, 0.5, s);
+  if (e != hipSuccess) return hip_fail(c, e, "yee_step");
+  c->step += 1;
+  return PIC_OK;
+}
+
+pic_status pic_sort(pic_ctx *c, pic_species *sp, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!species_ok(c, sp, true) || !sp->tile_start) return fail(c, PIC_EINVAL, "bad species (sort buffers)");
+  hipError_t e = pic::launch_sort(*c, *sp, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "sort");
+  c->pending_cell = nullptr;
+  return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f, int32_t nsteps, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (nspecies < 0 || (nspecies > 0 && !sp) || nsteps < 0) return fail(c, PIC_EINVAL, "bad counts");
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  for (int i = 0; i < nspecies; ++i)
+    if (!species_ok(c, &sp[i], true)) return fail(c, PIC_EINVAL, "bad species (pic_step needs sort buffers)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < nsteps; ++it) {
+    const bool cadence = (c->step % c->p.sort_every) == 0;
+    for (int i = 0; i < nspecies; ++i) {
+      if (sp[i].np > 0 && (cadence || !sp[i].sorted)) {
+        PhaseTimer t(c, s, pic::kPhaseSort);
+        e = pic::launch_sort(*c, sp[i], s);
+        if (e != hipSuccess) return hip_fail(c, e, "sort");
+      }
+    }
+    {
+      PhaseTimer t(c, s, pic::kPhaseZero);
+      for (int d = 0; d < 3 && e == hipSuccess; ++d) e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, s);
+      if (e != hipSuccess) return hip_fail(c, e, "zero_current");
+    }
+    for (int i = 0; i < nspecies; ++i) {
+      if (sp[i].np == 0) continue;
+      PhaseTimer t(c, s, pic::kPhasePush);
+      e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s);
+      if (e != hipSuccess) return hip_fail(c, e, "push_deposit");
+    }
+    {
+      PhaseTimer t(c, s, pic::kPhaseYee);
+      e = pic::launch_yee_b(*c, *f, 0.5, s);
+      if (e == hipSuccess) e = pic::launch_yee_e(*c, *f, s);
+      if (e == hipSuccess) e = pic::launch_yee_b(*c, *f, 0.5, s);
+      if (e != hipSuccess) return hip_fail(c, e, "yee");
+    }
+    c->step += 1;
+  }
+  c->pending_cell = nullptr;
+  return PIC_OK;
+}
+
+pic_status pic_diagnostics(pic_ctx *c, const pic_species *sp, int32_t nspecies, const pic_fields *f, double *out,
+                           void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!out || nspecies < 0 || nspecies > pic::kMaxSpecies || (nspecies > 0 && !sp))
+    return fail(c, PIC_EINVAL, "bad diagnostics arguments");
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  for (int i = 0; i < nspecies; ++i)
+    if (!species_ok(c, &sp[i], false)) return fail(c, PIC_EINVAL, "bad species");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool have_prev = c->diag_step >= 0;
+  const bool have_cont = have_prev && c->diag_step + 1 == c->step;
+  hipError_t e = pic::launch_diagnostics(*c, sp, nspecies, *f, have_prev, have_cont, s);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics");
+  double res[16];
+  e = hipMemcpyAsync(res, c->wsptr + c->ws.result, sizeof(double) * PIC_NDIAG, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics readback");
+  if (!have_prev) res[6] = NAN;
+  if (!have_cont) res[7] = NAN;
+  for (int i = 0; i < PIC_NDIAG; ++i) out[i] = res[i];
+  c->diag_step = c->step;
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(res[i])) return fail(c, PIC_ENAN, "non-finite energy or charge");
+  return pic_check(c, stream);
+}
+
+pic_status pic_check(pic_ctx *c, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t flags = 0;
+  hipError_t e = hipMemcpyAsync(&flags, c->wsptr + c->ws.flags, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "check");
+  if (flags != 0) {
+    const int32_t zero = 0;
+    e = hipMemcpyAsync(c->wsptr + c->ws.flags, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "check reset");
+    if (flags & pic::kFlagCross) return fail(c, PIC_ECROSS, pic_status_string(PIC_ECROSS));
+  }
+  return PIC_OK;
+}
+
+pic_status pic_set_timing(pic_ctx *c, int32_t on) {
+  if (!c) return PIC_EINVAL;
+  c->timing = on != 0;
+  return PIC_OK;
+}
+
+pic_status pic_get_timing(pic_ctx *c, double *ms, int64_t *launches, int32_t nphase) {
+  if (!c || !ms || !launches || nphase < 1) return PIC_EINVAL;
+  collect_timing(c);
+  for (int i = 0; i < nphase && i < PIC_NPHASE; ++i) {
+    ms[i] = c->ms[i];
+    launches[i] = c->launches[i];
+    c->ms[i] = 0.0;
+    c->launches[i] = 0;
+  }
+  return PIC_OK;
+}
+
+}  // extern "C"

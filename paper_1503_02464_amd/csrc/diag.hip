@@ -1,0 +1,245 @@
+// FP64 diagnostics: field and kinetic energy, total charge, the charge density
+// on nodes and the residuals of Gauss's law and of the continuity equation.
+// Sums run in double whatever the state precision; partial results go to
+// fixed slots and one workgroup reduces them in a fixed order, so the result
+// does not depend on scheduling (the charge grid itself is built with double
+// atomics, whose order does vary at round-off level).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "particle_math.h"
+#include "pic_internal.h"
+
+namespace pic {
+namespace {
+
+constexpr int kB = 256;
+constexpr int kStride = kMaxSpecies * kDiagBlocks;  // entries per slot
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < static_cast<int>(blockDim.x / 64); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o));
+  const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < static_cast<int>(blockDim.x / 64); ++i) r = fmax(r, sh[i]);
+  __syncthreads();
+  return r;
+}
+
+// Slots 0, 1: sum |E|^2, sum |B|^2 (scaled to energies by the final pass).
+template <typename T>
+__global__ void __launch_bounds__(kB) k_field_sq(const T *e0, const T *e1, const T *e2, const T *b0, const T *b1,
+                                                 const T *b2, int64_t n, double *partials) {
+  __shared__ double sh[16];
+  double se = 0.0, sb = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = e0[i], y = e1[i], z = e2[i];
+    se += x * x + y * y + z * z;
+    const double a = b0[i], b = b1[i], c = b2[i];
+    sb += a * a + b * b + c * c;
+  }
+  se = block_sum(se, sh);
+  sb = block_sum(sb, sh);
+  if (threadIdx.x == 0) {
+    partials[0 * kStride + blockIdx.x] = se;
+    partials[1 * kStride + blockIdx.x] = sb;
+  }
+}
+
+// Slots 2, 3: sum w m (gamma - 1), sum q w for one species (block range by species).
+template <typename T>
+__global__ void __launch_bounds__(kB) k_particle_sums(const T *u0, const T *u1, const T *u2, const T *w, int64_t np,
+                                                      double q, double m, double *partials, int slot0) {
+  __shared__ double sh[16];
+  double k = 0.0, qs = 0.0;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const double a = u0[p], b = u1[p], c = u2[p];
+    const double usq = a * a + b * b + c * c;
+    // gamma - 1 written without cancellation for slow particles
+    const double gm1 = usq / (sqrt(1.0 + usq) + 1.0);
+    k += static_cast<double>(w[p]) * m * gm1;
+    qs += q * static_cast<double>(w[p]);
+  }
+  k = block_sum(k, sh);
+  qs = block_sum(qs, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * kStride + slot0 + blockIdx.x] = k;
+    partials[3 * kStride + slot0 + blockIdx.x] = qs;
+  }
+}
+
+// Charge density on nodes: rho(node) += q w / dV * S(x - node), in double.
+template <typename T, int D, int M>
+__global__ void __launch_bounds__(kB) k_rho(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w,
+                                            int64_t np, double qdv, int b0, int b1, int m0, int m1, int m2, int n0,
+                                            int n1, int n2, double *rho) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const uint32_t pk = static_cast<uint32_t>(cell[p]);
+  int c[3] = {static_cast<int>(pk & m0), static_cast<int>((pk >> b0) & m1),
+              static_cast<int>((pk >> (b0 + b1)) & m2)};
+  c[0] = c[0] >= n0 ? c[0] - n0 : c[0];
+  c[1] = c[1] >= n1 ? c[1] - n1 : c[1];
+  c[2] = c[2] >= n2 ? c[2] - n2 : c[2];
+  const double o[3] = {static_cast<double>(o0[p]), static_cast<double>(o1[p]), D == 3 ? static_cast<double>(o2[p]) : 0.0};
+  double wx[M + 1], wy[M + 1], wz[M + 1];
+  int bx, by, bz = 0;
+  node_weights<double, M>(c[0], o[0], wx, bx);
+  node_weights<double, M>(c[1], o[1], wy, by);
+  if (D == 3) node_weights<double, M>(c[2], o[2], wz, bz);
+  const double a = qdv * static_cast<double>(w[p]);
+  const int kmax = D == 3 ? M : 0;
+  for (int k = 0; k <= kmax; ++k) {
+    const int gk = D == 3 ? wrap_near(bz + k, n2) : 0;
+    const double fz = D == 3 ? wz[k] : 1.0;
+    for (int j = 0; j <= M; ++j) {
+      const int gj = wrap_near(by + j, n1);
+      for (int i = 0; i <= M; ++i) {
+        const int gi = wrap_near(bx + i, n0);
+        unsafeAtomicAdd(&rho[gi + (int64_t)n0 * (gj + (int64_t)n1 * gk)], a * wx[i] * wy[j] * fz);
+      }
+    }
+  }
+}
+
+// Slots 4..7 per node: |rho|, |div E - rho|, |G - G_prev|, |(rho - rho_prev)/dt + div J|;
+// then the current rho and G become the previous ones.
+template <typename T, int D>
+__global__ void __launch_bounds__(kB) k_gauss(const T *ex, const T *ey, const T *ez, const T *jx, const T *jy,
+                                              const T *jz, const double *rho, double *rho_prev, double *g_prev,
+                                              int n0, int n1, int n2, double idx, double idy, double idz, double idt,
+                                              int have_prev, int have_cont, double *partials) {
+  __shared__ double sh[16];
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  double mr = 0.0, mg = 0.0, mdg = 0.0, mc = 0.0;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = static_cast<int>(o % n0);
+    const int j = static_cast<int>((o / n0) % n1);
+    const int k = static_cast<int>(o / ((int64_t)n0 * n1));
+    const int64_t im = i == 0 ? o + (n0 - 1) : o - 1;
+    const int64_t jm = j == 0 ? o + (int64_t)n0 * (n1 - 1) : o - n0;
+    const int64_t km = k == 0 ? o + (int64_t)n0 * n1 * (n2 - 1) : o - (int64_t)n0 * n1;
+    double dE = (static_cast<double>(ex[o]) - ex[im]) * idx + (static_cast<double>(ey[o]) - ey[jm]) * idy;
+    double dJ = (static_cast<double>(jx[o]) - jx[im]) * idx + (static_cast<double>(jy[o]) - jy[jm]) * idy;
+    if (D == 3) {
+      dE += (static_cast<double>(ez[o]) - ez[km]) * idz;
+      dJ += (static_cast<double>(jz[o]) - jz[km]) * idz;
+    }
+    const double r = rho[o];
+    const double g = dE - r;
+    mr = fmax(mr, fabs(r));
+    mg = fmax(mg, fabs(g));
+    if (have_prev) mdg = fmax(mdg, fabs(g - g_prev[o]));
+    if (have_cont) mc = fmax(mc, fabs((r - rho_prev[o]) * idt + dJ));
+    rho_prev[o] = r;
+    g_prev[o] = g;
+  }
+  mr = block_max(mr, sh);
+  mg = block_max(mg, sh);
+  mdg = block_max(mdg, sh);
+  mc = block_max(mc, sh);
+  if (threadIdx.x == 0) {
+    partials[4 * kStride + blockIdx.x] = mr;
+    partials[5 * kStride + blockIdx.x] = mg;
+    partials[6 * kStride + blockIdx.x] = mdg;
+    partials[7 * kStride + blockIdx.x] = mc;
+  }
+}
+
+// One workgroup: reduce slot s over cnt[s] entries (sum for 0..3, max for 4..7).
+__global__ void __launch_bounds__(1024) k_final(const double *partials, int cnt_fields, int cnt_particles,
+                                                int cnt_grid, double dv, double *result) {
+  __shared__ double sh[16];
+  for (int s = 0; s < kDiagSlots; ++s) {
+    const int cnt = s < 2 ? cnt_fields : (s < 4 ? cnt_particles : cnt_grid);
+    double v = 0.0;
+    if (s < 4) {
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) v += partials[s * kStride + i];
+      v = block_sum(v, sh);
+    } else {
+      for (int i = threadIdx.x; i < cnt; i += blockDim.x) v = fmax(v, partials[s * kStride + i]);
+      v = block_max(v, sh);
+    }
+    if (threadIdx.x == 0) result[s] = s < 2 ? 0.5 * v * dv : v;
+  }
+}
+
+template <typename T, int D, int M>
+hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_fields &f, bool have_prev, bool have_cont,
+               hipStream_t s) {
+  double *partials = c.wsp<double>(c.ws.partials);
+  double *rho = c.wsp<double>(c.ws.rho);
+  const int64_t n = c.ncells;
+  double dV = 1.0;
+  for (int d = 0; d < c.p.dims; ++d) dV *= c.p.dx[d];
+  int gblocks = static_cast<int>((n + kB - 1) / kB);
+  if (gblocks > kDiagBlocks) gblocks = kDiagBlocks;
+  hipLaunchKernelGGL(k_field_sq<T>, dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
+                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.B[0]),
+                     static_cast<const T *>(f.B[1]), static_cast<const T *>(f.B[2]), n, partials);
+  hipError_t e = launch_fill_zero(rho, n, 8, s);
+  if (e != hipSuccess) return e;
+  // clear the particle slots (species that are empty leave their blocks unused)
+  e = launch_fill_zero(partials + 2 * kStride, 2 * kStride, 8, s);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < nsp; ++i) {
+    const pic_species &q = sp[i];
+    if (q.np == 0) continue;
+    int pb = static_cast<int>((q.np + kB - 1) / kB);
+    if (pb > kDiagBlocks) pb = kDiagBlocks;
+    hipLaunchKernelGGL(k_particle_sums<T>, dim3(pb), dim3(kB), 0, s, static_cast<const T *>(q.u[0]),
+                       static_cast<const T *>(q.u[1]), static_cast<const T *>(q.u[2]), static_cast<const T *>(q.w),
+                       q.np, q.q, q.m, partials, i * kDiagBlocks);
+    const unsigned rb = static_cast<unsigned>((q.np + kB - 1) / kB);
+    hipLaunchKernelGGL((k_rho<T, D, M>), dim3(rb), dim3(kB), 0, s, q.cell, static_cast<const T *>(q.off[0]),
+                       static_cast<const T *>(q.off[1]), static_cast<const T *>(q.off[2]),
+                       static_cast<const T *>(q.w), q.np, q.q / dV, c.bits[0], c.bits[1], (1 << c.bits[0]) - 1,
+                       (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1, static_cast<int>(c.n[0]),
+                       static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), rho);
+  }
+  hipLaunchKernelGGL((k_gauss<T, D>), dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
+                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.J[0]),
+                     static_cast<const T *>(f.J[1]), static_cast<const T *>(f.J[2]), rho,
+                     c.wsp<double>(c.ws.rho_prev), c.wsp<double>(c.ws.gauss_prev), static_cast<int>(c.n[0]),
+                     static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), 1.0 / c.p.dx[0], 1.0 / c.p.dx[1],
+                     c.p.dims == 3 ? 1.0 / c.p.dx[2] : 0.0, 1.0 / c.p.dt, have_prev ? 1 : 0, have_cont ? 1 : 0,
+                     partials);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, partials, gblocks, kMaxSpecies * kDiagBlocks, gblocks, dV,
+                     c.wsp<double>(c.ws.result));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
+                              bool have_prev, bool have_cont, hipStream_t s) {
+  const bool f64 = c.p.precision == PIC_FP64;
+  const int key = (f64 ? 4 : 0) + (c.p.dims == 3 ? 2 : 0) + (c.p.shape_order - 1);
+  switch (key) {
+    case 0: return run<float, 2, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 1: return run<float, 2, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 2: return run<float, 3, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 3: return run<float, 3, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 4: return run<double, 2, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 5: return run<double, 2, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
+    case 6: return run<double, 3, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
+    default: return run<double, 3, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
+  }
+}
+
+}  // namespace pic

@@ -1,0 +1,94 @@
+// Internal declarations of the PIC library: the context, the workspace layout
+// and the kernel launchers (one per phase, dispatching on precision, number of
+// dimensions and shape order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = 8;         // species per diagnostics call
+constexpr int kDiagBlocks = 1024;      // partial sums per species / per grid pass
+constexpr int kDiagSlots = PIC_NDIAG;  // UE UB K Q max|rho| max|G| max|dG| max|cont|
+
+// Byte offsets of the workspace regions (each 256-byte aligned).
+struct Workspace {
+  size_t flags = 0;       // int32[64]: sticky device flags
+  size_t save_cell = 0;   // int32[max_particles]: packed cell at x^n (unfused path)
+  size_t save_off = 0;    // T[3][max_particles]: offsets at x^n (unfused path)
+  size_t sort_key = 0;    // int32[max_particles]
+  size_t sort_rank = 0;   // int32[max_particles]
+  size_t tile_count = 0;  // int32[ntiles + 1]
+  size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
+  size_t result = 0;      // double[16]
+  size_t rho = 0;         // double[ncells]
+  size_t rho_prev = 0;    // double[ncells]
+  size_t gauss_prev = 0;  // double[ncells]
+  size_t total = 0;
+};
+
+enum Flag : int32_t { kFlagCross = 1 };
+
+enum Phase { kPhaseSort = 0, kPhaseZero = 1, kPhasePush = 2, kPhaseYee = 3 };
+
+}  // namespace pic
+
+struct pic_ctx {
+  pic_params p{};
+  int64_t n[3] = {1, 1, 1};
+  int64_t ncells = 0;
+  int32_t bits[3] = {0, 0, 0};
+  int32_t ntile[3] = {1, 1, 1};
+  int64_t ntiles = 0;
+  size_t elem = 4;  // sizeof(float) or sizeof(double)
+  // LDS tile geometry of the fused kernel: field and current regions per
+  // dimension, starting gf_lo / gj_lo cells below the tile origin.
+  int32_t rf[3] = {1, 1, 1}, rj[3] = {1, 1, 1};
+  int32_t gf_lo[3] = {0, 0, 0}, gj_lo[3] = {0, 0, 0};
+  size_t lds_bytes = 0;
+  int32_t block = 256;  // threads per workgroup of the fused kernel
+  pic::Workspace ws;
+  char *wsptr = nullptr;
+  size_t wsbytes = 0;
+  // the species whose old positions the workspace holds (pic_gather_push -> pic_deposit)
+  const void *pending_cell = nullptr;
+  int64_t pending_np = -1;
+  int64_t step = 0;
+  int64_t diag_step = -1;  // step count at the previous pic_diagnostics call
+  // per-phase timing
+  bool timing = false;
+  struct Ev {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  std::vector<hipEvent_t> spare;
+  double ms[PIC_NPHASE] = {0, 0, 0, 0};
+  int64_t launches[PIC_NPHASE] = {0, 0, 0, 0};
+  std::string err;
+
+  template <typename X>
+  X *wsp(size_t off) const { return reinterpret_cast<X *>(wsptr + off); }
+};
+
+namespace pic {
+
+// Kernel launchers (device code in the .hip files).  Each returns the HIP
+// error of its launches.
+hipError_t launch_gather_push(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
+hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
+hipError_t launch_push_deposit_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
+hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
+hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s);
+hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s);
+hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s);
+hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
+                              bool have_prev, bool have_cont, hipStream_t s);
+
+}  // namespace pic

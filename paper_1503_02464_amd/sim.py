@@ -1,0 +1,271 @@
+"""Python face of the PIC library: torch tensors own the device memory, the
+library does every step of the computation.  This module only marshals
+arguments (pointers, sizes, the current HIP stream) and converts the
+per-dimension (cell, offset) particle form to the packed cell index."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def pack_cells(cell: np.ndarray, bits: tuple) -> np.ndarray:
+    """Per-dimension cell indices (3, np) -> packed int32: ix | iy << bx | iz << (bx + by)."""
+    c = np.asarray(cell, np.int64)
+    packed = c[0] | (c[1] << bits[0]) | (c[2] << (bits[0] + bits[1]))
+    return packed.astype(np.uint32).view(np.int32)
+
+
+def unpack_cells(packed: np.ndarray, bits: tuple) -> np.ndarray:
+    p = np.asarray(packed).view(np.uint32).astype(np.int64)
+    b0, b1, b2 = bits
+    out = np.zeros((3, p.shape[0]), np.int32)
+    out[0] = p & ((1 << b0) - 1)
+    out[1] = (p >> b0) & ((1 << b1) - 1)
+    out[2] = (p >> (b0 + b1)) & ((1 << b2) - 1)
+    return out
+
+
+def cell_bits(n: tuple, dims: int) -> tuple:
+    """Bits per dimension of the packed cell index: ceil(log2(n_d))."""
+    return tuple(int(np.ceil(np.log2(n[d]))) if d < dims and n[d] > 1 else 0 for d in range(3))
+
+
+@dataclass
+class SpeciesState:
+    """Device arrays of one species (two sets for the out-of-place sort)."""
+
+    q: float
+    m: float
+    np: int
+    sets: list  # two dicts: cell (int32), off (3 tensors), u (3 tensors), w
+    tile_start: torch.Tensor
+    struct: L.Species
+
+    def current(self) -> dict:
+        """The set the struct's primary pointers name (after sorts swapped them)."""
+        for s in self.sets:
+            if _ptr(s["cell"]) == self.struct.cell:
+                return s
+        raise RuntimeError("species pointers out of sync")
+
+
+class Simulation:
+    """One periodic box: grid parameters, E/B/J, workspace and species.
+
+    dims 2 or 3; n cells per dim (n[2] = 1 in 2D); dx spacings; dt step;
+    order 1 (linear) or 2 (quadratic); precision "fp32" or "fp64"; tile cells
+    per sort tile; slack guard cells; sort_every steps between sorts."""
+
+    def __init__(self, dims: int, n: tuple, dx: tuple, dt: float, order: int, precision: str = "fp32",
+                 tile: tuple = (8, 8, 8), slack: int = 1, sort_every: int = 4, max_particles: int = 0,
+                 device: str = "cuda"):
+        self.lib = L.load()
+        self.dims = dims
+        self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+        self.dx = tuple(float(v) for v in dx) + (1.0,) * (3 - len(dx))
+        self.dt = float(dt)
+        self.order = order
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.device = torch.device(device)
+        tile = tuple(tile) + (1,) * (3 - len(tile))
+        if dims == 2:
+            tile = (tile[0], tile[1], 1)
+        p = L.Params()
+        p.dims = dims
+        p.n = L._c3i(*self.n)
+        p.dx = L._c3d(*self.dx)
+        p.dt = self.dt
+        p.shape_order = order
+        p.precision = L.PIC_FP32 if precision == "fp32" else L.PIC_FP64
+        p.tile = L._c3i(*tile)
+        p.slack = slack
+        p.sort_every = sort_every
+        p.max_particles = int(max_particles)
+        self.params = p
+        ctx = ctypes.c_void_p()
+        st = self.lib.pic_init(ctypes.byref(p), ctypes.byref(ctx))
+        L.check(self.lib, None, st, "pic_init")
+        self.ctx = ctx
+        nbytes = self.lib.pic_workspace_bytes(ctx)
+        # 256-byte aligned workspace carved from a torch allocation
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = _ptr(self._ws)
+        aligned = (base + 255) & ~255
+        self._call(self.lib.pic_set_workspace(ctx, ctypes.c_void_p(aligned), nbytes), "pic_set_workspace")
+        self.ncells = self.n[0] * self.n[1] * self.n[2]
+        self.fields = {k: [torch.zeros(self.ncells, dtype=self.dtype, device=self.device) for _ in range(3)]
+                       for k in ("E", "B", "J")}
+        self.fstruct = L.Fields()
+        for k in ("E", "B", "J"):
+            setattr(self.fstruct, k, L._c3p(*[_ptr(t) for t in self.fields[k]]))
+        bits = (ctypes.c_int32 * 3)()
+        self.lib.pic_cell_bits(ctx, bits)
+        self.bits = tuple(bits)
+        self.ntiles = int(self.lib.pic_num_tiles(ctx))
+        self.species: list = []
+
+    # -- plumbing ---------------------------------------------------------
+    def _call(self, status: int, what: str) -> None:
+        L.check(self.lib, self.ctx, status, what)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            torch.cuda.synchronize()
+            self.lib.pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- data in / out ----------------------------------------------------
+    def pack_cells(self, cell: np.ndarray) -> np.ndarray:
+        return pack_cells(cell, self.bits)
+
+    def unpack_cells(self, packed: np.ndarray) -> np.ndarray:
+        return unpack_cells(packed, self.bits)
+
+    def set_fields(self, E=None, B=None, J=None) -> None:
+        for k, v in (("E", E), ("B", B), ("J", J)):
+            if v is None:
+                continue
+            for d in range(3):
+                self.fields[k][d].copy_(torch.as_tensor(np.asarray(v[d]), dtype=self.dtype))
+
+    def get_fields(self) -> dict:
+        torch.cuda.synchronize()
+        return {k: np.stack([t.double().cpu().numpy() for t in v]) for k, v in self.fields.items()}
+
+    def add_species(self, sp: dict, capacity: int | None = None) -> SpeciesState:
+        """Upload a species given as numpy arrays (per-dimension cells, offsets,
+        momenta, weights; see paper_1503_02464_amd.inputs)."""
+        npart = int(sp["w"].shape[0])
+        cap = max(npart, capacity or 0, 1)
+        dev, dt = self.device, self.dtype
+        sets = []
+        for _ in range(2):
+            sets.append({
+                "cell": torch.zeros(cap, dtype=torch.int32, device=dev),
+                "off": [torch.zeros(cap, dtype=dt, device=dev) for _ in range(3)],
+                "u": [torch.zeros(cap, dtype=dt, device=dev) for _ in range(3)],
+                "w": torch.zeros(cap, dtype=dt, device=dev),
+            })
+        s0 = sets[0]
+        if npart:
+            s0["cell"][:npart].copy_(torch.from_numpy(self.pack_cells(sp["cell"])))
+            for d in range(3):
+                s0["off"][d][:npart].copy_(torch.as_tensor(sp["off"][d], dtype=dt))
+                s0["u"][d][:npart].copy_(torch.as_tensor(sp["u"][d], dtype=dt))
+            s0["w"][:npart].copy_(torch.as_tensor(sp["w"], dtype=dt))
+        tile_start = torch.zeros(self.ntiles + 1, dtype=torch.int32, device=dev)
+        st = L.Species()
+        st.np = npart
+        st.q = float(sp["q"])
+        st.m = float(sp["m"])
+        self._fill_struct(st, sets[0], sets[1])
+        st.tile_start = _ptr(tile_start)
+        st.sorted = 0
+        state = SpeciesState(float(sp["q"]), float(sp["m"]), npart, sets, tile_start, st)
+        self.species.append(state)
+        return state
+
+    @staticmethod
+    def _fill_struct(st: L.Species, a: dict, b: dict) -> None:
+        st.cell = _ptr(a["cell"])
+        st.off = L._c3p(*[_ptr(t) for t in a["off"]])
+        st.u = L._c3p(*[_ptr(t) for t in a["u"]])
+        st.w = _ptr(a["w"])
+        st.cell_alt = _ptr(b["cell"])
+        st.off_alt = L._c3p(*[_ptr(t) for t in b["off"]])
+        st.u_alt = L._c3p(*[_ptr(t) for t in b["u"]])
+        st.w_alt = _ptr(b["w"])
+
+    def get_species(self, s: SpeciesState) -> dict:
+        torch.cuda.synchronize()
+        cur = s.current()
+        n = s.np
+        out = {"q": s.q, "m": s.m,
+               "cell": self.unpack_cells(cur["cell"][:n].cpu().numpy()),
+               "off": np.stack([t[:n].double().cpu().numpy() for t in cur["off"]]),
+               "u": np.stack([t[:n].double().cpu().numpy() for t in cur["u"]]),
+               "w": cur["w"][:n].double().cpu().numpy()}
+        if self.dims == 2:
+            out["off"][2] = 0.0
+        return out
+
+    def tile_start(self, s: SpeciesState) -> np.ndarray:
+        torch.cuda.synchronize()
+        return s.tile_start.cpu().numpy().astype(np.int64)
+
+    # -- the hot path -----------------------------------------------------
+    def gather_push(self, s: SpeciesState) -> None:
+        self._call(self.lib.pic_gather_push(self.ctx, ctypes.byref(s.struct), ctypes.byref(self.fstruct),
+                                            ctypes.c_void_p(_stream())), "pic_gather_push")
+
+    def deposit(self, s: SpeciesState) -> None:
+        self._call(self.lib.pic_deposit(self.ctx, ctypes.byref(s.struct), ctypes.byref(self.fstruct),
+                                        ctypes.c_void_p(_stream())), "pic_deposit")
+
+    def zero_current(self) -> None:
+        self._call(self.lib.pic_zero_current(self.ctx, ctypes.byref(self.fstruct), ctypes.c_void_p(_stream())),
+                   "pic_zero_current")
+
+    def yee_step(self) -> None:
+        self._call(self.lib.pic_yee_step(self.ctx, ctypes.byref(self.fstruct), ctypes.c_void_p(_stream())),
+                   "pic_yee_step")
+
+    def sort(self, s: SpeciesState) -> None:
+        self._call(self.lib.pic_sort(self.ctx, ctypes.byref(s.struct), ctypes.c_void_p(_stream())), "pic_sort")
+
+    def step(self, nsteps: int = 1, species: list | None = None) -> None:
+        sp = species if species is not None else self.species
+        arr = (L.Species * max(len(sp), 1))()
+        for i, s in enumerate(sp):
+            arr[i] = s.struct
+        self._call(self.lib.pic_step(self.ctx, arr, len(sp), ctypes.byref(self.fstruct), int(nsteps),
+                                     ctypes.c_void_p(_stream())), "pic_step")
+        for i, s in enumerate(sp):
+            s.struct = arr[i]
+
+    def diagnostics(self, species: list | None = None) -> dict:
+        sp = species if species is not None else self.species
+        arr = (L.Species * max(len(sp), 1))()
+        for i, s in enumerate(sp):
+            arr[i] = s.struct
+        out = (ctypes.c_double * L.PIC_NDIAG)()
+        self._call(self.lib.pic_diagnostics(self.ctx, arr, len(sp), ctypes.byref(self.fstruct), out,
+                                            ctypes.c_void_p(_stream())), "pic_diagnostics")
+        keys = ("UE", "UB", "K", "Q", "rho_max", "gauss_max", "gauss_change", "continuity")
+        return dict(zip(keys, list(out)))
+
+    def check(self) -> None:
+        self._call(self.lib.pic_check(self.ctx, ctypes.c_void_p(_stream())), "pic_check")
+
+    def set_timing(self, on: bool) -> None:
+        self._call(self.lib.pic_set_timing(self.ctx, 1 if on else 0), "pic_set_timing")
+
+    def get_timing(self) -> dict:
+        ms = (ctypes.c_double * L.PIC_NPHASE)()
+        cnt = (ctypes.c_int64 * L.PIC_NPHASE)()
+        self._call(self.lib.pic_get_timing(self.ctx, ms, cnt, L.PIC_NPHASE), "pic_get_timing")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.PHASES)}
+
+    @property
+    def step_count(self) -> int:
+        return int(self.lib.pic_step_count(self.ctx))

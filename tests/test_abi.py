@@ -1,0 +1,136 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and validates parameters on the host (no kernel runs)."""
+import ctypes
+import math
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1503_02464_amd import _lib as L
+from paper_1503_02464_amd import sim
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.load()
+
+
+def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec=L.PIC_FP32, tile=(8, 8, 8),
+           slack=1, sort_every=4, maxp=1000):
+    p = L.Params()
+    p.dims = dims
+    p.n = L._c3i(*n)
+    p.dx = L._c3d(*dx)
+    p.dt = cfl / math.sqrt(sum(1.0 / dx[d] ** 2 for d in range(min(dims, 3)) if dx[d] > 0))
+    p.shape_order = order
+    p.precision = prec
+    p.tile = L._c3i(*tile)
+    p.slack = slack
+    p.sort_every = sort_every
+    p.max_particles = maxp
+    return p
+
+
+def init(lib, p):
+    ctx = ctypes.c_void_p()
+    st = lib.pic_init(ctypes.byref(p), ctypes.byref(ctx))
+    return st, ctx
+
+
+def test_exports_every_declared_function(lib):
+    names = L.header_functions()
+    assert len(names) >= 20, names
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_valid_init_and_queries(lib):
+    st, ctx = init(lib, params())
+    assert st == L.PIC_OK
+    assert lib.pic_num_tiles(ctx) == 8
+    assert lib.pic_workspace_bytes(ctx) > 0
+    bits = (ctypes.c_int32 * 3)()
+    lib.pic_cell_bits(ctx, bits)
+    assert tuple(bits) == (4, 4, 4)
+    # LDS: fields (8+1+2+2)^3 * 6 + current (8+2+3+2)^3 * 3, FP32
+    assert lib.pic_tile_lds_bytes(ctx) == (13 ** 3 * 6 + 15 ** 3 * 3) * 4
+    assert lib.pic_step_count(ctx) == 0
+    lib.pic_destroy(ctx)
+
+
+@pytest.mark.parametrize("cfl,want", [(0.999, L.PIC_OK), (1.0, L.PIC_ECFL), (1.2, L.PIC_ECFL)])
+def test_cfl_limit(lib, cfl, want):
+    st, ctx = init(lib, params(cfl=cfl))
+    assert st == want
+    if st == L.PIC_OK:
+        lib.pic_destroy(ctx)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dims=4), dict(order=3), dict(prec=7), dict(tile=(5, 8, 8)), dict(tile=(8, 8, 0)),
+    dict(n=(16, 16, 2)), dict(dims=2, n=(16, 16, 4), tile=(8, 8, 1)), dict(dims=2, n=(16, 16, 1), tile=(8, 8, 2)),
+    dict(sort_every=0), dict(slack=5), dict(maxp=-1), dict(dx=(0.05, 0.0, 0.05)),
+    dict(prec=L.PIC_FP64, tile=(16, 16, 16), n=(32, 32, 32)),  # LDS tile beyond 160 KB
+])
+def test_invalid_params(lib, kw):
+    st, ctx = init(lib, params(**kw))
+    assert st == L.PIC_EINVAL, kw
+
+
+def test_calls_without_workspace_fail_cleanly(lib):
+    st, ctx = init(lib, params())
+    assert st == L.PIC_OK
+    sp = L.Species()
+    f = L.Fields()
+    assert lib.pic_gather_push(ctx, ctypes.byref(sp), ctypes.byref(f), None) == L.PIC_ENOMEM
+    assert lib.pic_step(ctx, ctypes.byref(sp), 1, ctypes.byref(f), 1, None) == L.PIC_ENOMEM
+    assert b"workspace" in lib.pic_last_error(ctx)
+    lib.pic_destroy(ctx)
+
+
+def test_header_and_binding_agree():
+    text = open(L.HEADER).read()
+    for name in ("PIC_OK = 0", "PIC_EINVAL = -1", "PIC_ECFL = -2", "PIC_EHIP = -3", "PIC_ENOMEM = -4",
+                 "PIC_ECROSS = -5", "PIC_ENAN = -6", "PIC_ESTATE = -7"):
+        assert name in text
+    assert "#define PIC_NDIAG 8" in text and "#define PIC_NPHASE 4" in text
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Offsets of every field of the three structs, from gcc on pic.h, equal the ctypes mirror."""
+    structs = {"pic_params": L.Params, "pic_fields": L.Fields, "pic_species": L.Species}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = L.HEADER.rsplit("/", 1)[0]
+    subprocess.check_call(["gcc", f"-I{inc}", "-o", str(exe), str(src)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {(a, b): int(c) for a, b, c in (l.split() for l in out if l.strip())}
+    for cname, cls in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_cell_packing_roundtrip():
+    r = np.random.default_rng(0)
+    for n, dims in (((256, 256, 256), 3), ((2048, 1024, 1), 2), ((512, 256, 256), 3), ((13, 7, 5), 3)):
+        bits = sim.cell_bits(n, dims)
+        assert sum(bits) <= 31
+        cell = np.zeros((3, 1000), np.int32)
+        for d in range(dims):
+            cell[d] = r.integers(0, n[d], 1000)
+        packed = sim.pack_cells(cell, bits)
+        assert packed.dtype == np.int32
+        assert np.array_equal(sim.unpack_cells(packed, bits), cell)

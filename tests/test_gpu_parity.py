@@ -1,0 +1,262 @@
+"""HIP library vs the FP64 oracle, element by element, on seeded inputs.
+
+FP64 path: 1e-12 (norm-relative for u, E, B, J; absolute cells for
+positions).  FP32 path (cell index + FP32 offset, FP32 momenta, fields and
+LDS current): the per-quantity tolerances in gpu_helpers.TOL."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import (TOL, by_weight, compare_fields, compare_species, grid, make_sim, pos_err, rel,
+                         state)
+from paper_1503_02464_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [(p, d, m) for p in ("fp64", "fp32") for d in (2, 3) for m in (1, 2)]
+VID = [f"{p}-{d}d-m{m}" for p, d, m in VARIANTS]
+
+
+def small_grid(dims, order, n2=(24, 20), n3=(16, 12, 8)):
+    return grid(dims, n2 if dims == 2 else n3, dx=0.05, cfl=0.7, order=order)
+
+
+def tiles(dims):
+    return (8, 4, 1) if dims == 2 else (8, 4, 4)
+
+
+@pytest.mark.parametrize("prec,dims", [(p, d) for p in ("fp64", "fp32") for d in (2, 3)])
+def test_yee_step(prec, dims):
+    g = small_grid(dims, 2)
+    f = inputs.random_fields(g.ncells, 1.0, seed=21)
+    f["J"] = inputs.rng(22).normal(size=(3, g.ncells))
+    if prec == "fp32":
+        f = inputs.round_fields_f32(f)
+    s = make_sim(g, prec, tiles(dims), max_particles=1)
+    s.set_fields(f["E"], f["B"], f["J"])
+    s.yee_step()
+    ref = {k: v.copy() for k, v in f.items()}
+    O.yee_step(g, ref)
+    compare_fields(prec, s.get_fields(), ref, keys=("E", "B"), what="yee")
+    s.close()
+
+
+@pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
+def test_unfused_gather_push_deposit(prec, dims, order):
+    g = small_grid(dims, order)
+    sp, f = state(g, prec, 3, 0.3, 0.2, seed=30 + dims + order, random_positions=False)
+    s = make_sim(g, prec, tiles(dims), max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.zero_current()
+    s.gather_push(h)
+    s.deposit(h)
+    s.check()
+    ref_sp = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    ref_f["J"][:] = 0
+    assert O.push_deposit(g, ref_f, ref_sp) == 0
+    compare_species(g, prec, s.get_species(h), ref_sp, "unfused")
+    compare_fields(prec, s.get_fields(), ref_f, keys=("J",), what="unfused")
+    s.close()
+
+
+TILE_CASES = {
+    # (tile, slack, particle layout): ragged occupancy, empty tiles, seam crossings
+    "uniform": (None, 1, "uniform"),
+    "slack0": (None, 0, "uniform"),
+    "clustered": (None, 2, "clustered"),
+    "one_tile": ("full", 1, "uniform"),
+}
+
+
+def clustered(g, prec, seed):
+    """Particles only in the lower half of x (empty tiles), random cells, so
+    tile counts are ragged."""
+    npart = g.ncells * 2
+    sp, f = state(g, prec, npart, 0.3, 0.2, seed, random_positions=True)
+    sp["cell"][0] = sp["cell"][0] % (g.n[0] // 2)
+    return sp, f
+
+
+@pytest.mark.parametrize("case", list(TILE_CASES))
+@pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
+def test_step_fused(prec, dims, order, case):
+    tile, slack, layout = TILE_CASES[case]
+    # one tile spanning the whole box: a smaller 3D box keeps it within 160 KB of LDS
+    g = small_grid(dims, order, n3=(8, 6, 4)) if tile == "full" else small_grid(dims, order)
+    tile = tuple(g.n) if tile == "full" else tiles(dims)
+    if layout == "uniform":
+        sp, f = state(g, prec, 3, 0.3, 0.2, seed=40 + dims + order)
+    else:
+        sp, f = clustered(g, prec, seed=50 + dims + order)
+    s = make_sim(g, prec, tile, slack=slack, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    compare_species(g, prec, s.get_species(h), ref_sp, f"fused {case}")
+    compare_fields(prec, s.get_fields(), ref_f, what=f"fused {case}")
+    s.close()
+
+
+@pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
+def test_sort(prec, dims, order):
+    g = small_grid(dims, order)
+    sp, _ = clustered(g, prec, seed=60)
+    tile = tiles(dims)
+    s = make_sim(g, prec, tile, max_particles=sp["w"].shape[0])
+    h = s.add_species(sp)
+    s.sort(h)
+    out = s.get_species(h)
+    start = s.tile_start(h)
+    keys = O.tile_keys(g, tile, out["cell"])
+    assert np.all(np.diff(keys) >= 0), "keys not sorted"
+    ref, ref_start = O.tile_sort(g, tile, sp)
+    assert np.array_equal(start, ref_start), "tile offsets differ"
+    # per tile the same particles (the order inside a tile is unspecified)
+    a, b = by_weight(out), by_weight(ref)
+    assert np.array_equal(a["w"], b["w"])
+    for k in ("cell", "off", "u"):
+        assert np.array_equal(a[k], b[k]), k
+    s.close()
+
+
+def test_c1_100_steps_fp64():
+    """The small 2D workload (64x64, 4 ppc, linear, 0.7 CFL) for 100 steps, FP64."""
+    from paper_1503_02464_amd.configs import c1_small_2d
+    w = c1_small_2d()
+    g = grid(2, w.n[:2], dx=w.dx[0], cfl=w.cfl, order=w.order)
+    sp = inputs.uniform_plasma(w.n, 2, w.ppc, w.u_sigma, w.weight, w.seed)
+    from gpu_helpers import unique_weights
+    sp = unique_weights(sp, 7, scale=w.weight)
+    s = make_sim(g, "fp64", w.tile, sort_every=4, max_particles=sp["w"].shape[0])
+    h = s.add_species(sp)
+    ref_sp = O.copy_species(sp)
+    ref_f = O.new_fields(g)
+    errs = []
+    for step in range(w.steps):
+        s.step(1)
+        O.step(g, ref_f, [ref_sp])
+        if step % 25 == 24 or step == w.steps - 1:
+            got = s.get_species(h)
+            gf = s.get_fields()
+            a, b = by_weight(got), by_weight(ref_sp)
+            errs.append((step, pos_err(g, a, b), rel(a["u"], b["u"]), rel(gf["E"], ref_f["E"])))
+    s.check()
+    last = errs[-1]
+    assert last[1] < 1e-12 and last[2] < 1e-12 and last[3] < 1e-12, errs
+    s.close()
+
+
+@pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
+def test_diagnostics(prec, dims, order):
+    g = small_grid(dims, order)
+    sp, f = state(g, prec, 3, 0.3, 0.05, seed=70)
+    s = make_sim(g, prec, tiles(dims), max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    d0 = s.diagnostics()
+    ref = O.diagnostics(g, f, [sp])
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(d0["UE"] - ref["UE"]) <= tol * ref["UE"]
+    assert abs(d0["UB"] - ref["UB"]) <= tol * ref["UB"]
+    # gamma - 1 of slow particles: the oracle's sqrt(1+u^2) - 1 loses ~1e-16/u^2 relative
+    assert abs(d0["K"] - ref["K"]) <= max(tol, 1e-10) * ref["K"]
+    assert abs(d0["Q"] - ref["Q"]) <= 1e-12 * abs(ref["Q"])
+    assert abs(d0["rho_max"] - np.max(np.abs(ref["rho"]))) <= tol * np.max(np.abs(ref["rho"]))
+    assert abs(d0["gauss_max"] - np.max(np.abs(ref["gauss"]))) <= max(tol, 1e-12) * np.max(np.abs(ref["gauss"]))
+    assert np.isnan(d0["gauss_change"]) and np.isnan(d0["continuity"])
+    s.step(1)
+    d1 = s.diagnostics()
+    # continuity and Gauss's law hold to round-off on the GPU path too
+    scale = d1["rho_max"]
+    eps = 1e-13 if prec == "fp64" else 2e-6
+    assert d1["continuity"] <= eps * scale / g.dt, (d1["continuity"], scale / g.dt)
+    assert d1["gauss_change"] <= eps * scale * 10, (d1["gauss_change"], scale)
+    assert abs(d1["Q"] - d0["Q"]) <= 1e-13 * abs(d0["Q"])
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_empty_and_tiny_species(prec):
+    """np = 0 alongside a species of one particle; a particle exactly on a node and one on the seam."""
+    g = small_grid(3, 2)
+    sp, f = state(g, prec, 3, 0.3, 0.2, seed=80, random_positions=True)
+    sp["cell"][:, 0] = [g.n[0] - 1, 0, g.n[2] - 1]
+    sp["off"][:, 0] = [0.0, 0.5, 0.999]
+    sp["off"][:, 1] = [0.0, 0.0, 0.0]
+    empty = {"q": 1.0, "m": 1836.0, "cell": np.zeros((3, 0), np.int32), "off": np.zeros((3, 0)),
+             "u": np.zeros((3, 0)), "w": np.zeros(0)}
+    s = make_sim(g, prec, tiles(3), max_particles=3)
+    s.set_fields(f["E"], f["B"])
+    he = s.add_species(empty)
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    O.step(g, ref_f, [ref_sp])
+    compare_species(g, prec, s.get_species(h), ref_sp, "tiny")
+    compare_fields(prec, s.get_fields(), ref_f, what="tiny")
+    assert s.get_species(he)["w"].shape[0] == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fast_and_slow_particles(prec):
+    """Displacements near the one-cell limit (gamma ~ 50) and tiny ones (cold
+    heavy ions, ~1e-6 cells) in the same step."""
+    g = small_grid(3, 2)
+    sp, f = state(g, prec, 2, 0.0, 0.01, seed=90)
+    npart = sp["w"].shape[0]
+    r = inputs.rng(91)
+    fast = r.random(npart) < 0.3
+    u = r.normal(size=(3, npart))
+    u = u / np.linalg.norm(u, axis=0) * np.where(fast, 50.0, 1e-4)
+    sp["u"] = np.ascontiguousarray(u.astype(np.float32).astype(np.float64) if prec == "fp32" else u)
+    s = make_sim(g, prec, tiles(3), max_particles=npart)
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    O.step(g, ref_f, [ref_sp])
+    compare_species(g, prec, s.get_species(h), ref_sp, "fast/slow")
+    compare_fields(prec, s.get_fields(), ref_f, what="fast/slow")
+    s.close()
+
+
+def test_non_finite_particle_is_flagged_and_frozen():
+    """A NaN momentum (forced from the host) is reported as PIC_ECROSS by the
+    next check; that particle stays put and deposits nothing, the others are exact."""
+    from paper_1503_02464_amd import _lib as L
+    g = small_grid(2, 1)
+    sp, f = state(g, "fp64", 2, 0.3, 0.1, seed=95)
+    bad = int(np.argmax(sp["w"]))
+    sp["u"][0, bad] = np.nan
+    s = make_sim(g, "fp64", tiles(2), max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    with pytest.raises(L.PicError) as ei:
+        s.check()
+    assert ei.value.status == L.PIC_ECROSS
+    s.check()  # the flag is cleared after it is reported
+    got = by_weight(s.get_species(h))
+    keep = np.ones(sp["w"].shape[0], bool)
+    keep[bad] = False
+    ref_sp = {k: (v[..., keep] if isinstance(v, np.ndarray) else v) for k, v in sp.items()}
+    ref_sp = O.copy_species(ref_sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    O.step(g, ref_f, [ref_sp])
+    last = got["w"].shape[0] - 1  # the NaN particle has the largest weight
+    assert got["cell"][0, last] == sp["cell"][0, bad] and got["off"][0, last] == sp["off"][0, bad]
+    rest = {k: (v[..., :last] if isinstance(v, np.ndarray) else v) for k, v in got.items()}
+    compare_species(g, "fp64", rest, ref_sp, "nan neighbours")
+    compare_fields("fp64", s.get_fields(), ref_f, keys=("J",), what="nan neighbours")
+    s.close()
