@@ -77,6 +77,12 @@ typedef enum {
 
 enum { PIC_FP32 = 0, PIC_FP64 = 1 };
 
+/* Accumulation type of the on-chip current tile of the fused kernel.  AUTO
+ * (the default) is FP64 for both precisions: on gfx950 LDS float atomics in
+ * double cost about a third of those in single precision, and the wider
+ * accumulator is also more accurate.  FP32 is accepted for an FP32 state. */
+enum { PIC_ACC_AUTO = 0, PIC_ACC_FP32 = 1, PIC_ACC_FP64 = 2 };
+
 /* The "grid" element of the paper's object model (Sec. 3.2). */
 typedef struct {
     int32_t dims;          /* 2 (2D3V) or 3 (3D3V) */
@@ -91,6 +97,7 @@ typedef struct {
                               and still take the on-chip path */
     int32_t sort_every;    /* pic_step re-sorts every this many steps (>= 1) */
     int64_t max_particles; /* the largest np of any species used with this context */
+    int32_t current_accum; /* PIC_ACC_AUTO, PIC_ACC_FP32 (FP32 state only) or PIC_ACC_FP64 */
 } pic_params;
 
 /* The "em-field" element (Sec. 3.2): E, B and J as nine device arrays of
@@ -188,6 +195,11 @@ pic_status pic_check(pic_ctx *ctx, void *stream);
 #define PIC_NPHASE 4
 pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
 pic_status pic_get_timing(pic_ctx *ctx, double *ms, int64_t *launches, int32_t nphase);
+
+/* Number of particles the last fused launch handed to the HBM path because
+ * their cell was more than `slack` cells outside their tile (synchronising).
+ * A large value means the species should be sorted more often. */
+pic_status pic_straggler_count(pic_ctx *ctx, int64_t *count, void *stream);
 
 /* Step counter (pic_step and pic_yee_step each count one per step). */
 int64_t pic_step_count(const pic_ctx *ctx);

@@ -13,6 +13,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "pic.h")
 
 PIC_OK, PIC_EINVAL, PIC_ECFL, PIC_EHIP, PIC_ENOMEM, PIC_ECROSS, PIC_ENAN, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 PIC_FP32, PIC_FP64 = 0, 1
+PIC_ACC_AUTO, PIC_ACC_FP32, PIC_ACC_FP64 = 0, 1, 2
 PIC_NDIAG = 8
 PIC_NPHASE = 4
 PHASES = ("sort", "zero_current", "push_deposit", "yee")
@@ -34,6 +35,7 @@ class Params(ctypes.Structure):
         ("slack", ctypes.c_int32),
         ("sort_every", ctypes.c_int32),
         ("max_particles", ctypes.c_int64),
+        ("current_accum", ctypes.c_int32),
     ]
 
 
@@ -99,6 +101,7 @@ def load(path: str = LIB_PATH):
         "pic_set_timing": (st, [ctx, ctypes.c_int32]),
         "pic_get_timing": (st, [ctx, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]),
         "pic_step_count": (ctypes.c_int64, [ctx]),
+        "pic_straggler_count": (st, [ctx, P(ctypes.c_int64), ctypes.c_void_p]),
         "pic_last_error": (ctypes.c_char_p, [ctx]),
         "pic_status_string": (ctypes.c_char_p, [st]),
     }

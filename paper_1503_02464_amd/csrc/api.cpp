@@ -132,11 +132,15 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   if (p->precision != PIC_FP32 && p->precision != PIC_FP64) return PIC_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t(1) << 31) - 1) return PIC_EINVAL;
   if (p->sort_every < 1 || p->slack < 0 || p->slack > 4) return PIC_EINVAL;
+  if (p->current_accum != PIC_ACC_AUTO && p->current_accum != PIC_ACC_FP32 && p->current_accum != PIC_ACC_FP64)
+    return PIC_EINVAL;
+  if (p->precision == PIC_FP64 && p->current_accum == PIC_ACC_FP32) return PIC_EINVAL;
   for (int d = 0; d < 3; ++d) {
     const bool used = d < p->dims;
     if (used) {
       if (p->n[d] < 4 || !(p->dx[d] > 0.0) || !std::isfinite(p->dx[d])) return PIC_EINVAL;
       if (p->tile[d] < 1 || p->n[d] % p->tile[d] != 0) return PIC_EINVAL;
+      if (p->tile[d] + p->slack > 31) return PIC_EINVAL;  // local cells are packed in 6 bits
     } else {
       if (p->n[d] != 1 || p->tile[d] != 1) return PIC_EINVAL;
     }
@@ -165,6 +169,8 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
     c->ntiles *= c->ntile[d];
   }
   c->elem = p->precision == PIC_FP64 ? 8 : 4;
+  c->acc64 = p->current_accum != PIC_ACC_FP32;
+  const size_t jelem = c->acc64 ? 8 : 4;
   // LDS tile geometry: the gather reaches [c-1, c+M] around the particle's
   // cell, the Esirkepov window [c-M, c+M+1]; slack widens both on each side.
   const int M = p->shape_order;
@@ -180,13 +186,19 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
       c->rf[d] = c->rj[d] = 1;
     }
   }
-  c->lds_bytes = (6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] +
-                  3 * static_cast<size_t>(c->rj[0]) * c->rj[1] * c->rj[2]) *
-                 c->elem;
-  if (c->lds_bytes > 160 * 1024) {
+  const size_t boxes = 6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] * c->elem +
+                       3 * static_cast<size_t>(c->rj[0]) * c->rj[1] * c->rj[2] * jelem;
+  if (boxes + pic::cross_list_bytes(c->elem, 0) > pic::kLdsLimit) {
     delete c;
     return PIC_EINVAL;
   }
+  // the wide-window list takes what is left, in multiples of 64 entries
+  const size_t entry = 8 * c->elem + 4;
+  int cap = c->elem == 4 ? pic::kCrossCapF32 : pic::kCrossCapF64;
+  const size_t room = (pic::kLdsLimit - boxes - pic::cross_list_bytes(c->elem, 0)) / entry;
+  if (static_cast<size_t>(cap) > room) cap = static_cast<int>(room / 64 * 64);
+  c->cross_cap = cap;
+  c->lds_bytes = boxes + pic::cross_list_bytes(c->elem, cap);
   // workspace layout
   pic::Workspace &w = c->ws;
   size_t off = 0;
@@ -201,7 +213,17 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.save_off = take(3 * mp * c->elem);
   w.sort_key = take(mp * 4);
   w.sort_rank = take(mp * 4);
-  w.tile_count = take((static_cast<size_t>(c->ntiles) + 1) * 4);
+  w.stray_count = take(4);
+  w.stray_list = take(mp * 4);
+  const int64_t nbuckets = c->ntiles * c->levels;
+  if (pic::sort_scan_blocks(nbuckets) > pic::sort_scan_capacity()) {
+    delete c;
+    return PIC_EINVAL;
+  }
+  w.tile_count = take(static_cast<size_t>(nbuckets) * 4);
+  w.bucket_start = take((static_cast<size_t>(nbuckets) + 1) * 4);
+  w.scan_partials = take(static_cast<size_t>(pic::sort_scan_blocks(nbuckets)) * 8);
+  w.node_count = take(static_cast<size_t>(ncells) * 4);
   w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
   w.result = take(16 * 8);
   w.rho = take(static_cast<size_t>(ncells) * 8);
@@ -389,6 +411,18 @@ pic_status pic_check(pic_ctx *c, void *stream) {
     if (e != hipSuccess) return hip_fail(c, e, "check reset");
     if (flags & pic::kFlagCross) return fail(c, PIC_ECROSS, pic_status_string(PIC_ECROSS));
   }
+  return PIC_OK;
+}
+
+pic_status pic_straggler_count(pic_ctx *c, int64_t *count, void *stream) {
+  if (!c || !count) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int32_t n = 0;
+  hipError_t e = hipMemcpyAsync(&n, c->wsptr + c->ws.stray_count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "straggler count");
+  *count = n;
   return PIC_OK;
 }
 

@@ -117,6 +117,75 @@ __global__ void __launch_bounds__(kB) k_rho(const int32_t *cell, const T *o0, co
   }
 }
 
+// The same on sorted particles, one workgroup per tile: the tile's charge is
+// accumulated in an LDS box (double) and added to HBM once.  Particles whose
+// cell lies more than `slack` cells outside their tile add to HBM directly.
+template <typename T, int D, int M>
+__global__ void __launch_bounds__(256) k_rho_tiled(const int32_t *cell, const T *o0, const T *o1, const T *o2,
+                                                   const T *w, const int32_t *tile_start, double qdv, int b0,
+                                                   int b1, int m0, int m1, int m2, int n0, int n1, int n2, int L0,
+                                                   int L1, int L2, int nt0, int nt1, int slack, double *rho) {
+  extern __shared__ double box[];
+  const int64_t tile = blockIdx.x;
+  const int64_t pbeg = tile_start[tile], pend = tile_start[tile + 1];
+  if (pbeg >= pend) return;
+  const int T0[3] = {static_cast<int>(tile % nt0) * L0, static_cast<int>((tile / nt0) % nt1) * L1,
+                     static_cast<int>(tile / ((int64_t)nt0 * nt1)) * L2};
+  const int lo = 1 + slack;
+  const int bx = L0 + 2 * slack + 3, by = L1 + 2 * slack + 3, bz = D == 3 ? L2 + 2 * slack + 3 : 1;
+  const int vol = bx * by * bz;
+  for (int i = threadIdx.x; i < vol; i += blockDim.x) box[i] = 0.0;
+  __syncthreads();
+  const int n[3] = {n0, n1, n2};
+  for (int64_t p = pbeg + threadIdx.x; p < pend; p += blockDim.x) {
+    const uint32_t pk = static_cast<uint32_t>(cell[p]);
+    int c[3] = {static_cast<int>(pk & m0), static_cast<int>((pk >> b0) & m1), static_cast<int>((pk >> (b0 + b1)) & m2)};
+    bool inside = true;
+    int lc[3] = {0, 0, 0};
+    for (int d = 0; d < D; ++d) {
+      c[d] = c[d] >= n[d] ? c[d] - n[d] : c[d];
+      int l = c[d] - T0[d];
+      if (l > n[d] / 2) l -= n[d];
+      if (l < -n[d] / 2) l += n[d];
+      lc[d] = l;
+      const int L = d == 0 ? L0 : (d == 1 ? L1 : L2);
+      inside = inside && l >= -slack && l < L + slack;
+    }
+    const double o[3] = {static_cast<double>(o0[p]), static_cast<double>(o1[p]), D == 3 ? static_cast<double>(o2[p]) : 0.0};
+    double wx[M + 1], wy[M + 1], wz[M + 1];
+    int ix, iy, iz = 0;
+    node_weights<double, M>(inside ? lc[0] : c[0], o[0], wx, ix);
+    node_weights<double, M>(inside ? lc[1] : c[1], o[1], wy, iy);
+    if (D == 3) node_weights<double, M>(inside ? lc[2] : c[2], o[2], wz, iz);
+    const double a = qdv * static_cast<double>(w[p]);
+    const int kmax = D == 3 ? M : 0;
+    for (int k = 0; k <= kmax; ++k) {
+      const double fz = D == 3 ? wz[k] : 1.0;
+      for (int j = 0; j <= M; ++j)
+        for (int i = 0; i <= M; ++i) {
+          const double v = a * wx[i] * wy[j] * fz;
+          if (inside) {
+            atomicAdd(&box[(ix + i + lo) + bx * ((iy + j + lo) + by * (D == 3 ? iz + k + lo : 0))], v);
+          } else {
+            const int gi = wrap_near(ix + i, n0), gj = wrap_near(iy + j, n1), gk = D == 3 ? wrap_near(iz + k, n2) : 0;
+            unsafeAtomicAdd(&rho[gi + (int64_t)n0 * (gj + (int64_t)n1 * gk)], v);
+          }
+        }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < vol; idx += blockDim.x) {
+    const double v = box[idx];
+    if (v == 0.0) continue;
+    const int li = idx % bx, lj = (idx / bx) % by, lk = idx / (bx * by);
+    int gi = (T0[0] - lo + li) % n0, gj = (T0[1] - lo + lj) % n1, gk = D == 3 ? (T0[2] - lo + lk) % n2 : 0;
+    gi = gi < 0 ? gi + n0 : gi;
+    gj = gj < 0 ? gj + n1 : gj;
+    gk = gk < 0 ? gk + n2 : gk;
+    unsafeAtomicAdd(&rho[gi + (int64_t)n0 * (gj + (int64_t)n1 * gk)], v);
+  }
+}
+
 // Slots 4..7 per node: |rho|, |div E - rho|, |G - G_prev|, |(rho - rho_prev)/dt + div J|;
 // then the current rho and G become the previous ones.
 template <typename T, int D>
@@ -205,6 +274,20 @@ hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_field
     hipLaunchKernelGGL(k_particle_sums<T>, dim3(pb), dim3(kB), 0, s, static_cast<const T *>(q.u[0]),
                        static_cast<const T *>(q.u[1]), static_cast<const T *>(q.u[2]), static_cast<const T *>(q.w),
                        q.np, q.q, q.m, partials, i * kDiagBlocks);
+    if (q.sorted && q.tile_start) {
+      const int sl = c.p.slack;
+      size_t box = static_cast<size_t>(c.p.tile[0] + 2 * sl + 3) * (c.p.tile[1] + 2 * sl + 3) *
+                   (D == 3 ? c.p.tile[2] + 2 * sl + 3 : 1) * sizeof(double);
+      if (box <= 64 * 1024) {
+        hipLaunchKernelGGL((k_rho_tiled<T, D, M>), dim3(static_cast<unsigned>(c.ntiles)), dim3(kB), box, s, q.cell,
+                           static_cast<const T *>(q.off[0]), static_cast<const T *>(q.off[1]),
+                           static_cast<const T *>(q.off[2]), static_cast<const T *>(q.w), q.tile_start, q.q / dV,
+                           c.bits[0], c.bits[1], (1 << c.bits[0]) - 1, (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1,
+                           static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), static_cast<int>(c.n[2]),
+                           c.p.tile[0], c.p.tile[1], c.p.tile[2], c.ntile[0], c.ntile[1], sl, rho);
+        continue;
+      }
+    }
     const unsigned rb = static_cast<unsigned>((q.np + kB - 1) / kB);
     hipLaunchKernelGGL((k_rho<T, D, M>), dim3(rb), dim3(kB), 0, s, q.cell, static_cast<const T *>(q.off[0]),
                        static_cast<const T *>(q.off[1]), static_cast<const T *>(q.off[2]),

@@ -221,114 +221,162 @@ __device__ __forceinline__ void esirkepov_axis(T o0, int dc, T o1, int &base, T 
   }
 }
 
-// Esirkepov current of one particle moving from (c0 + o0) to (c0 + dc + o1).
-//   J_x(i+1/2) - J_x(i-1/2) = -(q w / dV)(dx/dt) W_x(i), and in 3D
-//   W_x = DS_x (S0_y S0_z + DS_y S0_z / 2 + S0_y DS_z / 2 + DS_y DS_z / 3)
-// so J_x over the window is -(q w/dV)(dx/dt) * CDS_x[i] * T_x[j][k] with
-// CDS the running sum of DS along x and T_x[j][k] = a_y[j] S0_z[k] + b_y[j] DS_z[k],
-// a = S0 + DS/2, b = S0/2 + DS/3 (cyclic for y and z).  In 2D3V J_z is the
-// time average of the shape product times v_z.  jc[d] = (q w/dV)(dx_d/dt),
-// jzc = q w v_z / dV.  Zero contributions are skipped.
-template <typename T, int D, int M, class Acc>
-__device__ __forceinline__ void deposit(const Acc &acc, const int c0[3], const T o0[3], const int dc[3], const T o1[3],
-                                        const T jc[3], T jzc) {
-  constexpr int W = M + 2;
+// Whether a move from (o0) to (dc + o1) changes the nearest node (M = 2) or
+// the cell (M = 1) on some axis: such a particle needs the M + 2 wide window.
+template <typename T, int D, int M>
+__device__ __forceinline__ bool crosses(const T o0[3], const int dc[3], const T o1[3]) {
+  bool c = false;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    if constexpr (M == 2) {
+      const int n0 = o0[d] >= T(0.5) ? 1 : 0;
+      const int n1 = dc[d] + (o1[d] >= T(0.5) ? 1 : 0);
+      c = c || n1 != n0;
+    } else {
+      c = c || dc[d] != 0;
+    }
+  }
+  return c;
+}
+
+// Per-particle Esirkepov factors on all axes (window of W = M + 2 nodes per
+// axis starting at node old cell + b[d]): the old shape S0, DS = new - old,
+// CDS = running sum of DS, A = S0 + DS/2, Bf = S0/2 + DS/3.  cross is true
+// when the nearest node (M = 2) or the cell (M = 1) changed on some axis;
+// otherwise every factor vanishes beyond the first M + 1 window slots.
+template <typename T, int M>
+struct Esirk {
+  static constexpr int W = M + 2;
   T S0[3][W], DS[3][W], CDS[3][W - 1], A[3][W], Bf[3][W];
-  int b[3] = {0, 0, 0};
+  int b[3];
+  bool cross;
+};
+
+template <typename T, int D, int M>
+__device__ __forceinline__ void esirkepov_factors(const T o0[3], const int dc[3], const T o1[3], Esirk<T, M> &e) {
+  constexpr int W = M + 2;
+  e.cross = false;
+  e.b[0] = e.b[1] = e.b[2] = 0;
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     bool cross;
-    esirkepov_axis<T, M>(o0[d], dc[d], o1[d], b[d], S0[d], DS[d], cross);
+    esirkepov_axis<T, M>(o0[d], dc[d], o1[d], e.b[d], e.S0[d], e.DS[d], cross);
+    e.cross = e.cross || cross;
     T run = T(0);
 #pragma unroll
     for (int i = 0; i < W - 1; ++i) {
-      run += DS[d][i];
-      CDS[d][i] = run;
+      run += e.DS[d][i];
+      e.CDS[d][i] = run;
     }
-    if (!cross) CDS[d][W - 2] = T(0);  // the sum of DS over the window vanishes
+    if (!cross) e.CDS[d][W - 2] = T(0);  // the sum of DS over the window vanishes
 #pragma unroll
     for (int i = 0; i < W; ++i) {
-      A[d][i] = S0[d][i] + T(0.5) * DS[d][i];
-      Bf[d][i] = T(0.5) * S0[d][i] + DS[d][i] * T(1.0 / 3.0);
+      e.A[d][i] = e.S0[d][i] + T(0.5) * e.DS[d][i];
+      e.Bf[d][i] = T(0.5) * e.S0[d][i] + e.DS[d][i] * T(1.0 / 3.0);
     }
   }
-  const int x0 = c0[0] + b[0], y0 = c0[1] + b[1], z0 = (D == 3) ? c0[2] + b[2] : 0;
+}
+
+// Esirkepov current of one particle:
+//   J_x(i+1/2) - J_x(i-1/2) = -(q w / dV)(dx/dt) W_x(i), and in 3D
+//   W_x = DS_x (S0_y S0_z + DS_y S0_z / 2 + S0_y DS_z / 2 + DS_y DS_z / 3)
+// so J_x over the window is -(q w/dV)(dx/dt) * CDS_x[i] * T_x[j][k] with
+// T_x[j][k] = A_y[j] S0_z[k] + Bf_y[j] DS_z[k] (cyclic for y and z).  In 2D3V
+// J_z is the time average of the shape product times v_z.  jc[d] = (q w/dV)(dx_d/dt),
+// jzc = q w v_z / dV.  FAST (no axis crossed a node): the window is M + 1
+// nodes per axis and every add is issued; otherwise M + 2 nodes and exact
+// zeros are skipped.
+template <typename T, int D, int M, bool FAST, class Acc>
+__device__ __forceinline__ void esirkepov_accumulate(const Acc &acc, const int c0[3], const Esirk<T, M> &e,
+                                                     const T jc[3], T jzc) {
+  constexpr int WJ = FAST ? M + 1 : M + 2;  // nodes across
+  constexpr int WI = WJ - 1;                // staggered points along
+  const int x0 = c0[0] + e.b[0], y0 = c0[1] + e.b[1], z0 = (D == 3) ? c0[2] + e.b[2] : 0;
   if constexpr (D == 3) {
-    // J_x
 #pragma unroll
-    for (int k = 0; k < W; ++k)
+    for (int k = 0; k < WJ; ++k)
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const T t = A[1][j] * S0[2][k] + Bf[1][j] * DS[2][k];
-        if (t != T(0)) {
+      for (int j = 0; j < WJ; ++j) {
+        const T t = e.A[1][j] * e.S0[2][k] + e.Bf[1][j] * e.DS[2][k];
+        if (FAST || t != T(0)) {
 #pragma unroll
-          for (int i = 0; i < W - 1; ++i) {
-            const T v = -jc[0] * CDS[0][i] * t;
-            if (v != T(0)) acc.add(0, x0 + i, y0 + j, z0 + k, v);
+          for (int i = 0; i < WI; ++i) {
+            const T v = -jc[0] * e.CDS[0][i] * t;
+            if (FAST || v != T(0)) acc.add(0, x0 + i, y0 + j, z0 + k, v);
           }
         }
       }
-    // J_y
 #pragma unroll
-    for (int k = 0; k < W; ++k)
+    for (int k = 0; k < WJ; ++k)
 #pragma unroll
-      for (int i = 0; i < W; ++i) {
-        const T t = A[0][i] * S0[2][k] + Bf[0][i] * DS[2][k];
-        if (t != T(0)) {
+      for (int i = 0; i < WJ; ++i) {
+        const T t = e.A[0][i] * e.S0[2][k] + e.Bf[0][i] * e.DS[2][k];
+        if (FAST || t != T(0)) {
 #pragma unroll
-          for (int j = 0; j < W - 1; ++j) {
-            const T v = -jc[1] * CDS[1][j] * t;
-            if (v != T(0)) acc.add(1, x0 + i, y0 + j, z0 + k, v);
+          for (int j = 0; j < WI; ++j) {
+            const T v = -jc[1] * e.CDS[1][j] * t;
+            if (FAST || v != T(0)) acc.add(1, x0 + i, y0 + j, z0 + k, v);
           }
         }
       }
-    // J_z
 #pragma unroll
-    for (int j = 0; j < W; ++j)
+    for (int j = 0; j < WJ; ++j)
 #pragma unroll
-      for (int i = 0; i < W; ++i) {
-        const T t = A[0][i] * S0[1][j] + Bf[0][i] * DS[1][j];
-        if (t != T(0)) {
+      for (int i = 0; i < WJ; ++i) {
+        const T t = e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j];
+        if (FAST || t != T(0)) {
 #pragma unroll
-          for (int k = 0; k < W - 1; ++k) {
-            const T v = -jc[2] * CDS[2][k] * t;
-            if (v != T(0)) acc.add(2, x0 + i, y0 + j, z0 + k, v);
+          for (int k = 0; k < WI; ++k) {
+            const T v = -jc[2] * e.CDS[2][k] * t;
+            if (FAST || v != T(0)) acc.add(2, x0 + i, y0 + j, z0 + k, v);
           }
         }
       }
   } else {
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const T t = A[1][j];
-      if (t != T(0)) {
+    for (int j = 0; j < WJ; ++j) {
+      const T t = e.A[1][j];
+      if (FAST || t != T(0)) {
 #pragma unroll
-        for (int i = 0; i < W - 1; ++i) {
-          const T v = -jc[0] * CDS[0][i] * t;
-          if (v != T(0)) acc.add(0, x0 + i, y0 + j, 0, v);
+        for (int i = 0; i < WI; ++i) {
+          const T v = -jc[0] * e.CDS[0][i] * t;
+          if (FAST || v != T(0)) acc.add(0, x0 + i, y0 + j, 0, v);
         }
       }
     }
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const T t = A[0][i];
-      if (t != T(0)) {
+    for (int i = 0; i < WJ; ++i) {
+      const T t = e.A[0][i];
+      if (FAST || t != T(0)) {
 #pragma unroll
-        for (int j = 0; j < W - 1; ++j) {
-          const T v = -jc[1] * CDS[1][j] * t;
-          if (v != T(0)) acc.add(1, x0 + i, y0 + j, 0, v);
+        for (int j = 0; j < WI; ++j) {
+          const T v = -jc[1] * e.CDS[1][j] * t;
+          if (FAST || v != T(0)) acc.add(1, x0 + i, y0 + j, 0, v);
         }
       }
     }
-    if (jzc != T(0)) {
+    if (FAST || jzc != T(0)) {
 #pragma unroll
-      for (int j = 0; j < W; ++j)
+      for (int j = 0; j < WJ; ++j)
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-          const T v = jzc * (A[0][i] * S0[1][j] + Bf[0][i] * DS[1][j]);
-          if (v != T(0)) acc.add(2, x0 + i, y0 + j, 0, v);
+        for (int i = 0; i < WJ; ++i) {
+          const T v = jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j]);
+          if (FAST || v != T(0)) acc.add(2, x0 + i, y0 + j, 0, v);
         }
     }
   }
+}
+
+// Esirkepov current of one particle moving from (c0 + o0) to (c0 + dc + o1).
+template <typename T, int D, int M, class Acc>
+__device__ __forceinline__ void deposit(const Acc &acc, const int c0[3], const T o0[3], const int dc[3], const T o1[3],
+                                        const T jc[3], T jzc) {
+  Esirk<T, M> e;
+  esirkepov_factors<T, D, M>(o0, dc, o1, e);
+  if (!e.cross)
+    esirkepov_accumulate<T, D, M, true>(acc, c0, e, jc, jzc);
+  else
+    esirkepov_accumulate<T, D, M, false>(acc, c0, e, jc, jzc);
 }
 
 // ---- accessors ------------------------------------------------------------
@@ -369,12 +417,28 @@ struct LdsFields {
   }
 };
 
-template <typename T>
+// The same with compile-time strides and origin, so every offset of the
+// (M+1)^D stencil folds into the LDS instruction's immediate offset.  S is
+// the stored type; values added are converted to it.
+template <typename S, int SX, int SXY, int VOL, int OX, int OY, int OZ>
+struct LdsBox {
+  S *base;
+  __device__ __forceinline__ S load(int comp, int i, int j, int k) const {
+    return base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)];
+  }
+  template <typename V>
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
+    atomicAdd(&base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)], static_cast<S>(v));
+  }
+};
+
+template <typename S>
 struct LdsCurrent {
-  T *base;
+  S *base;
   int sx, sxy, vol, o0, o1, o2;
-  __device__ __forceinline__ void add(int comp, int i, int j, int k, T v) const {
-    atomicAdd(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], v);
+  template <typename V>
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
+    atomicAdd(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], static_cast<S>(v));
   }
 };
 

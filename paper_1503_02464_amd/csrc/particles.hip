@@ -133,6 +133,23 @@ __global__ void __launch_bounds__(256) k_deposit(SpeciesArgs<T> s, GridArgs g, G
 // ---------------------------------------------------------------------------
 // Fused per-tile kernel.
 // ---------------------------------------------------------------------------
+// Local cell (within [-32, 32) of the tile origin) and cell change per axis in one int.
+__device__ __forceinline__ int32_t pack_local(const int lc[3], const int dc[3]) {
+  int32_t v = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v |= (((lc[d] + 32) & 63) | ((dc[d] + 1) << 6)) << (8 * d);
+  return v;
+}
+
+__device__ __forceinline__ void unpack_local(int32_t v, int lc[3], int dc[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int b = (v >> (8 * d)) & 255;
+    lc[d] = (b & 63) - 32;
+    dc[d] = (b >> 6) - 1;
+  }
+}
+
 struct TileArgs {
   const int32_t *tile_start;
   int L[3];       // tile size
@@ -141,13 +158,75 @@ struct TileArgs {
   int rf[3], rj[3];        // LDS field / current box sizes
   int gf_lo[3], gj_lo[3];  // box origins below the tile origin
   int remap;               // 1: spread consecutive tiles over XCDs in blocks
+  int32_t *stray_count;    // particles left outside their LDS box (handled by k_stragglers)
+  int32_t *stray_list;
+  int cross_cap;           // entries of the LDS list of wide-window particles
 };
 
-template <typename T, int D, int M>
-__global__ void __launch_bounds__(256) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
-                                                            GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
+// Tile geometry known at compile time: LDS offsets fold into immediates.
+template <int D, int M, int LX, int LY, int LZ, int SL>
+struct FixedGeom {
+  static constexpr int L0 = LX, L1 = LY, L2 = D == 3 ? LZ : 1, S = SL;
+  static constexpr int FLO = 1 + SL, JLO = M + SL;
+  static constexpr int FX = LX + 1 + M + 2 * SL, FY = LY + 1 + M + 2 * SL, FZ = D == 3 ? LZ + 1 + M + 2 * SL : 1;
+  static constexpr int JX = LX + 2 * M + 1 + 2 * SL, JY = LY + 2 * M + 1 + 2 * SL,
+                       JZ = D == 3 ? LZ + 2 * M + 1 + 2 * SL : 1;
+  static constexpr int FVOL = FX * FY * FZ, JVOL = JX * JY * JZ;
+  __device__ explicit FixedGeom(const TileArgs &) {}
+};
+
+// Tile geometry from the launch arguments (any tile shape).
+struct RuntimeGeom {
+  int L0, L1, L2, S, FLO, JLO, FX, FY, FZ, JX, JY, JZ, FVOL, JVOL;
+  __device__ explicit RuntimeGeom(const TileArgs &t)
+      : L0(t.L[0]), L1(t.L[1]), L2(t.L[2]), S(t.slack), FLO(t.gf_lo[0]), JLO(t.gj_lo[0]), FX(t.rf[0]), FY(t.rf[1]),
+        FZ(t.rf[2]), JX(t.rj[0]), JY(t.rj[1]), JZ(t.rj[2]), FVOL(t.rf[0] * t.rf[1] * t.rf[2]),
+        JVOL(t.rj[0] * t.rj[1] * t.rj[2]) {}
+};
+
+template <typename T, class G, int D>
+struct FieldBox;
+template <typename T, class G, int D>
+struct CurrentBox;
+
+template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
+struct FieldBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
+  using G = FixedGeom<D, M, LX, LY, LZ, SL>;
+  using type = LdsBox<T, G::FX, G::FX * G::FY, G::FVOL, G::FLO, G::FLO, D == 3 ? G::FLO : 0>;
+  __device__ static type make(T *base, const G &) { return type{base}; }
+};
+template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
+struct CurrentBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
+  using G = FixedGeom<D, M, LX, LY, LZ, SL>;
+  using type = LdsBox<T, G::JX, G::JX * G::JY, G::JVOL, G::JLO, G::JLO, D == 3 ? G::JLO : 0>;
+  __device__ static type make(T *base, const G &) { return type{base}; }
+};
+template <typename T, int DD>
+struct FieldBox<T, RuntimeGeom, DD> {
+  using type = LdsFields<T>;
+  __device__ static type make(T *base, const RuntimeGeom &g) {
+    return type{base, g.FX, g.FX * g.FY, g.FVOL, -g.FLO, -g.FLO, DD == 3 ? -g.FLO : 0};
+  }
+};
+template <typename T, int DD>
+struct CurrentBox<T, RuntimeGeom, DD> {
+  using type = LdsCurrent<T>;
+  __device__ static type make(T *base, const RuntimeGeom &g) {
+    return type{base, g.JX, g.JX * g.JY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0};
+  }
+};
+
+// One workgroup per tile of sorted particles: stage E and B of the tile plus
+// guards in LDS, push every particle whose cell lies within the slack of
+// the tile (gather from LDS, Boris, move, Esirkepov into an LDS current box
+// held in TJ), then add the current box into J in HBM.  Particles further
+// out are listed for k_stragglers.
+template <typename T, int D, int M, class G, int BLOCK, typename TJ>
+__global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
+                                                              GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *smem = reinterpret_cast<T *>(smem_raw);
+  const G geo(t);
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
   // contiguous range of tiles so neighbouring tiles share its L2.
   int64_t tile = blockIdx.x;
@@ -160,38 +239,43 @@ __global__ void __launch_bounds__(256) k_push_deposit_tiled(SpeciesArgs<T> s, Gr
   const int tx = static_cast<int>(tile % t.ntile[0]);
   const int ty = static_cast<int>((tile / t.ntile[0]) % t.ntile[1]);
   const int tz = static_cast<int>(tile / ((int64_t)t.ntile[0] * t.ntile[1]));
-  const int T0[3] = {tx * t.L[0], ty * t.L[1], tz * t.L[2]};
+  const int T0[3] = {tx * geo.L0, ty * geo.L1, tz * geo.L2};
 
-  const int fvol = t.rf[0] * t.rf[1] * t.rf[2];
-  const int jvol = t.rj[0] * t.rj[1] * t.rj[2];
   T *fl = smem;
-  T *jl = smem + 6 * fvol;
+  TJ *jl = reinterpret_cast<TJ *>(smem + 6 * geo.FVOL);  // 6 * FVOL * sizeof(T) is a multiple of 8
+  // Particles whose nearest node changes are deposited after the main loop,
+  // all together, so that the wide-window path runs with full wavefronts.
+  const int CAP = t.cross_cap;
+  T *xo = reinterpret_cast<T *>(jl + 3 * geo.JVOL);  // [6][CAP]: old then new offsets
+  T *xw = xo + 6 * CAP;                               // [2][CAP]: weight, 2D v_z factor
+  int32_t *xk = reinterpret_cast<int32_t *>(xw + 2 * CAP);  // [CAP]: local cell and cell change
+  int32_t *xn = xk + CAP;                                    // list length
+  if (threadIdx.x == 0) *xn = 0;
 
   // stage E, B of the tile plus guards (periodic wrap)
-  for (int idx = threadIdx.x; idx < fvol; idx += blockDim.x) {
-    const int li = idx % t.rf[0];
-    const int lj = (idx / t.rf[0]) % t.rf[1];
-    const int lk = idx / (t.rf[0] * t.rf[1]);
-    int gi = T0[0] - t.gf_lo[0] + li, gjj = T0[1] - t.gf_lo[1] + lj, gk = T0[2] - t.gf_lo[2] + lk;
-    gi = wrap_full(gi, g.n[0]);
-    gjj = wrap_full(gjj, g.n[1]);
-    gk = D == 3 ? wrap_full(gk, g.n[2]) : 0;
+  for (int idx = threadIdx.x; idx < geo.FVOL; idx += BLOCK) {
+    const int li = idx % geo.FX;
+    const int lj = (idx / geo.FX) % geo.FY;
+    const int lk = idx / (geo.FX * geo.FY);
+    const int gi = wrap_full(T0[0] - geo.FLO + li, g.n[0]);
+    const int gjj = wrap_full(T0[1] - geo.FLO + lj, g.n[1]);
+    const int gk = D == 3 ? wrap_full(T0[2] - geo.FLO + lk, g.n[2]) : 0;
     const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) fl[c * fvol + idx] = gf.F[c][gidx];
+    for (int c = 0; c < 6; ++c) fl[c * geo.FVOL + idx] = gf.F[c][gidx];
   }
-  for (int idx = threadIdx.x; idx < 3 * jvol; idx += blockDim.x) jl[idx] = T(0);
+  for (int idx = threadIdx.x; idx < 3 * geo.JVOL; idx += BLOCK) jl[idx] = TJ(0);
   __syncthreads();
 
   // local frames: the tile origin is (0,0,0)
-  const LdsFields<T> lf{fl, t.rf[0], t.rf[0] * t.rf[1], fvol, -t.gf_lo[0], -t.gf_lo[1], D == 3 ? -t.gf_lo[2] : 0};
-  const LdsCurrent<T> lj{jl, t.rj[0], t.rj[0] * t.rj[1], jvol, -t.gj_lo[0], -t.gj_lo[1], D == 3 ? -t.gj_lo[2] : 0};
+  const auto lf = FieldBox<T, G, D>::make(fl, geo);
+  const auto lj = CurrentBox<TJ, G, D>::make(jl, geo);
+  const int lane = __lane_id();
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  for (int64_t p = pbeg + threadIdx.x; p < pend; p += blockDim.x) {
+  for (int64_t p = pbeg + threadIdx.x; p < pend; p += BLOCK) {
     int c[3];
     unpack(s.cell[p], g, c);
-    T o[3], u[3];
-    load_particle<T, D>(s, p, o, u);
     // cell relative to the tile origin, unwrapped across the periodic seam
     int lc[3] = {0, 0, 0};
     bool inside = true;
@@ -201,13 +285,22 @@ __global__ void __launch_bounds__(256) k_push_deposit_tiled(SpeciesArgs<T> s, Gr
       if (l > g.n[d] / 2) l -= g.n[d];
       if (l < -g.n[d] / 2) l += g.n[d];
       lc[d] = l;
-      inside = inside && (l >= -t.slack) && (l < t.L[d] + t.slack);
+      const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
+      inside = inside && (l >= -geo.S) && (l < L + geo.S);
     }
+    const uint64_t out = __ballot(!inside);
+    if (out) {  // list the particles outside the box for the HBM path
+      const int leader = __ffsll(static_cast<unsigned long long>(out)) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(t.stray_count, __popcll(out));
+      base = __shfl(base, leader);
+      if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
+    }
+    if (!inside) continue;
+    T o[3], u[3];
+    load_particle<T, D>(s, p, o, u);
     T eb[6];
-    if (inside)
-      gather_eb<T, D, M>(lf, lc, o, eb);
-    else
-      gather_eb<T, D, M>(gf, c, o, eb);
+    gather_eb<T, D, M>(lf, lc, o, eb);
     boris<T>(u, eb, s.h);
     const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     T on[3] = {T(0), T(0), T(0)};
@@ -215,13 +308,39 @@ __global__ void __launch_bounds__(256) k_push_deposit_tiled(SpeciesArgs<T> s, Gr
     const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
     if (!ok) atomicOr(&flags[0], kFlagCross);
     const T w = s.w[p];
-    const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-    const T jz = D == 2 ? w * s.jz * u[2] * ig : T(0);
-    if (ok) {
-      if (inside)
-        deposit<T, D, M>(lj, lc, o, dc, on, jc, jz);
-      else
-        deposit<T, D, M>(gj, c, o, dc, on, jc, jz);
+    const T jz = D == 2 ? s.jz * u[2] * ig : T(0);
+    const bool wide = ok && crosses<T, D, M>(o, dc, on);
+    if (ok && !wide) {
+      Esirk<T, M> e;
+      esirkepov_factors<T, D, M>(o, dc, on, e);
+      const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+      esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
+    }
+    // one LDS atomic per wavefront reserves list slots for the wide ones
+    const uint64_t wm = __ballot(wide);
+    if (wm) {
+      const int leader = __ffsll(static_cast<unsigned long long>(wm)) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(xn, __popcll(wm));
+      base = __shfl(base, leader);
+      if (wide) {
+        const int k = base + __popcll(wm & below);
+        if (k < CAP) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            xo[d * CAP + k] = o[d];
+            xo[(3 + d) * CAP + k] = on[d];
+          }
+          xw[k] = w;
+          xw[CAP + k] = jz;
+          xk[k] = pack_local(lc, dc);
+        } else {  // list full: deposit here
+          Esirk<T, M> e;
+          esirkepov_factors<T, D, M>(o, dc, on, e);
+          const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+          esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * jz);
+        }
+      }
     }
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -235,20 +354,76 @@ __global__ void __launch_bounds__(256) k_push_deposit_tiled(SpeciesArgs<T> s, Gr
   }
   __syncthreads();
 
-  // merge the current tile into HBM (skipping cells nothing touched)
-  for (int idx = threadIdx.x; idx < jvol; idx += blockDim.x) {
-    const int li = idx % t.rj[0];
-    const int lj2 = (idx / t.rj[0]) % t.rj[1];
-    const int lk = idx / (t.rj[0] * t.rj[1]);
-    const int gi = wrap_full(T0[0] - t.gj_lo[0] + li, g.n[0]);
-    const int gjj = wrap_full(T0[1] - t.gj_lo[1] + lj2, g.n[1]);
-    const int gk = D == 3 ? wrap_full(T0[2] - t.gj_lo[2] + lk, g.n[2]) : 0;
+  // the listed particles, with every lane busy
+  const int nx = *xn < CAP ? *xn : CAP;
+  for (int k = threadIdx.x; k < nx; k += BLOCK) {
+    T o0[3], o1[3];
+    int lc[3], dc[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o0[d] = xo[d * CAP + k];
+      o1[d] = xo[(3 + d) * CAP + k];
+    }
+    unpack_local(xk[k], lc, dc);
+    const T w = xw[k];
+    Esirk<T, M> e;
+    esirkepov_factors<T, D, M>(o0, dc, o1, e);
+    const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+    esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
+  }
+  __syncthreads();
+
+  // add the current box into HBM (skipping cells nothing touched)
+  for (int idx = threadIdx.x; idx < geo.JVOL; idx += BLOCK) {
+    const int li = idx % geo.JX;
+    const int lj2 = (idx / geo.JX) % geo.JY;
+    const int lk = idx / (geo.JX * geo.JY);
+    const int gi = wrap_full(T0[0] - geo.JLO + li, g.n[0]);
+    const int gjj = wrap_full(T0[1] - geo.JLO + lj2, g.n[1]);
+    const int gk = D == 3 ? wrap_full(T0[2] - geo.JLO + lk, g.n[2]) : 0;
     const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const T v = jl[c * jvol + idx];
+      const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
       if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
     }
+  }
+}
+
+// The particles a tiled launch left outside their LDS box: full step with
+// fields and current in HBM.
+template <typename T, int D, int M>
+__global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
+                                                    GlobalCurrent<T> gj, const int32_t *count, const int32_t *list,
+                                                    int32_t *flags) {
+  const int64_t n = *count;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = list[k];
+    int c[3];
+    unpack(s.cell[p], g, c);
+    T o[3], u[3];
+    load_particle<T, D>(s, p, o, u);
+    T eb[6];
+    gather_eb<T, D, M>(gf, c, o, eb);
+    boris<T>(u, eb, s.h);
+    const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    T on[3] = {T(0), T(0), T(0)};
+    int dc[3] = {0, 0, 0};
+    const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
+    if (!ok) atomicOr(&flags[0], kFlagCross);
+    const T w = s.w[p];
+    const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+    const T jz = D == 2 ? w * s.jz * u[2] * ig : T(0);
+    if (ok) deposit<T, D, M>(gj, c, o, dc, on, jc, jz);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = wrap_near(c[d] + dc[d], g.n[d]);
+      s.off[d][p] = on[d];
+    }
+    s.cell[p] = pack(c, g);
+    s.u[0][p] = u[0];
+    s.u[1][p] = u[1];
+    s.u[2][p] = u[2];
   }
 }
 
@@ -331,6 +506,36 @@ hipError_t deposit_impl(const pic_ctx &c, const pic_species &sp, const pic_field
   return hipGetLastError();
 }
 
+template <typename T, int D, int M, class G, int BLOCK, typename TJ>
+hipError_t launch_tiled_acc(const pic_ctx &c, const pic_species &sp, const pic_fields &f, const TileArgs &t,
+                            hipStream_t st) {
+  const auto kern = k_push_deposit_tiled<T, D, M, G, BLOCK, TJ>;
+  const size_t lds = c.lds_bytes;
+  static size_t lds_set = 0;  // largest dynamic LDS size granted to this instantiation
+  if (lds > 65536 && lds > lds_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    lds_set = lds;
+  }
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(c.ntiles)), dim3(BLOCK), lds, st, species_args<T>(c, sp),
+                     grid_args(c), global_fields<T>(c, f), global_current<T>(c, f), t, c.wsp<int32_t>(c.ws.flags));
+  return hipGetLastError();
+}
+
+// The LDS current box is accumulated in double unless the caller asked for
+// FP32 accumulation of an FP32 state.
+template <typename T, int D, int M, class G, int BLOCK>
+hipError_t launch_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, const TileArgs &t,
+                        hipStream_t st) {
+  if constexpr (sizeof(T) == 4) {
+    if (!c.acc64) return launch_tiled_acc<T, D, M, G, BLOCK, float>(c, sp, f, t, st);
+  }
+  return launch_tiled_acc<T, D, M, G, BLOCK, double>(c, sp, f, t, st);
+}
+
+// Tile shapes with a compile-time instantiation; other shapes use the
+// runtime-geometry kernel.
 template <typename T, int D, int M>
 hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t st) {
   if (sp.np == 0) return hipSuccess;
@@ -346,17 +551,33 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
   }
   t.slack = c.p.slack;
   t.remap = (c.ntiles % 8 == 0 && c.ntiles >= 64) ? 1 : 0;
-  const auto kern = k_push_deposit_tiled<T, D, M>;
-  const size_t lds = c.lds_bytes;
-  static size_t lds_set = 0;  // largest dynamic LDS size granted to this instantiation
-  if (lds > 65536 && lds > lds_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    lds_set = lds;
+  t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
+  t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
+  t.cross_cap = c.cross_cap;
+  hipError_t e = launch_fill_zero(t.stray_count, 1, 4, st);
+  if (e != hipSuccess) return e;
+  const int *L = c.p.tile;
+  const int sl = c.p.slack;
+  constexpr int BIG = sizeof(T) == 4 ? 1024 : 512;  // threads per workgroup of the fixed-shape kernels
+  if constexpr (D == 3) {
+    if (sizeof(T) == 4 && L[0] == 8 && L[1] == 8 && L[2] == 8 && sl == 1)
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 8, 1>, BIG>(c, sp, f, t, st);
+    else if (L[0] == 8 && L[1] == 8 && L[2] == 4 && sl == 1)
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 4, 1>, BIG>(c, sp, f, t, st);
+    else
+      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sp, f, t, st);
+  } else {
+    if (L[0] == 16 && L[1] == 16 && sl == 1)
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sp, f, t, st);
+    else
+      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sp, f, t, st);
   }
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(c.ntiles)), dim3(c.block), lds, st, species_args<T>(c, sp),
-                     grid_args(c), global_fields<T>(c, f), global_current<T>(c, f), t, c.wsp<int32_t>(c.ws.flags));
+  if (e != hipSuccess) return e;
+  int64_t blocks = (sp.np + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL((k_stragglers<T, D, M>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     species_args<T>(c, sp), grid_args(c), global_fields<T>(c, f), global_current<T>(c, f),
+                     t.stray_count, t.stray_list, c.wsp<int32_t>(c.ws.flags));
   return hipGetLastError();
 }
 

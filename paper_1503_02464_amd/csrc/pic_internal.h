@@ -16,6 +16,15 @@ namespace pic {
 constexpr int kMaxSpecies = 8;         // species per diagnostics call
 constexpr int kDiagBlocks = 1024;      // partial sums per species / per grid pass
 constexpr int kDiagSlots = PIC_NDIAG;  // UE UB K Q max|rho| max|G| max|dG| max|cont|
+// Largest capacity of the fused kernel's list of particles that need the
+// wide Esirkepov window (their nearest node changed), per precision; the
+// context lowers it to what the LDS left by the field and current boxes holds.
+constexpr int kCrossCapF32 = 512;
+constexpr int kCrossCapF64 = 256;
+constexpr size_t kLdsLimit = 160 * 1024;
+// LDS bytes of a list of cap entries: old and new offsets, weight, v_z
+// factor, packed cell; plus its length.
+inline size_t cross_list_bytes(size_t elem, int cap) { return static_cast<size_t>(cap) * (8 * elem + 4) + 16; }
 
 // Byte offsets of the workspace regions (each 256-byte aligned).
 struct Workspace {
@@ -24,7 +33,12 @@ struct Workspace {
   size_t save_off = 0;    // T[3][max_particles]: offsets at x^n (unfused path)
   size_t sort_key = 0;    // int32[max_particles]
   size_t sort_rank = 0;   // int32[max_particles]
-  size_t tile_count = 0;  // int32[ntiles + 1]
+  size_t stray_count = 0; // int32: particles the tiled kernel left outside their LDS box
+  size_t stray_list = 0;  // int32[max_particles]: their indices
+  size_t tile_count = 0;  // int32[ntiles * levels]: particles per (tile, level) bucket
+  size_t bucket_start = 0;   // int32[ntiles * levels + 1]
+  size_t scan_partials = 0;  // int64[scan blocks]
+  size_t node_count = 0;     // int32[ncells]: particles per nearest node (level ranks)
   size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
   size_t result = 0;      // double[16]
   size_t rho = 0;         // double[ncells]
@@ -52,7 +66,9 @@ struct pic_ctx {
   int32_t rf[3] = {1, 1, 1}, rj[3] = {1, 1, 1};
   int32_t gf_lo[3] = {0, 0, 0}, gj_lo[3] = {0, 0, 0};
   size_t lds_bytes = 0;
-  int32_t block = 256;  // threads per workgroup of the fused kernel
+  bool acc64 = true;  // LDS current box accumulated in double
+  int32_t cross_cap = 0;  // capacity of the fused kernel's wide-window list
+  int32_t levels = 16;  // rank levels per tile in the sort (particles sharing a node go to distinct levels)
   pic::Workspace ws;
   char *wsptr = nullptr;
   size_t wsbytes = 0;
@@ -88,6 +104,8 @@ hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s);
 hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s);
 hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s);
+int64_t sort_scan_blocks(int64_t nbuckets);
+int64_t sort_scan_capacity();
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
                               bool have_prev, bool have_cont, hipStream_t s);
 

@@ -67,11 +67,12 @@ class Simulation:
 
     dims 2 or 3; n cells per dim (n[2] = 1 in 2D); dx spacings; dt step;
     order 1 (linear) or 2 (quadratic); precision "fp32" or "fp64"; tile cells
-    per sort tile; slack guard cells; sort_every steps between sorts."""
+    per sort tile; slack guard cells; sort_every steps between sorts;
+    current_accum the LDS current accumulation type ("auto" = fp64)."""
 
     def __init__(self, dims: int, n: tuple, dx: tuple, dt: float, order: int, precision: str = "fp32",
                  tile: tuple = (8, 8, 8), slack: int = 1, sort_every: int = 4, max_particles: int = 0,
-                 device: str = "cuda"):
+                 current_accum: str = "auto", device: str = "cuda"):
         self.lib = L.load()
         self.dims = dims
         self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
@@ -95,6 +96,7 @@ class Simulation:
         p.slack = slack
         p.sort_every = sort_every
         p.max_particles = int(max_particles)
+        p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64}[current_accum]
         self.params = p
         ctx = ctypes.c_void_p()
         st = self.lib.pic_init(ctypes.byref(p), ctypes.byref(ctx))
@@ -265,6 +267,13 @@ class Simulation:
         cnt = (ctypes.c_int64 * L.PIC_NPHASE)()
         self._call(self.lib.pic_get_timing(self.ctx, ms, cnt, L.PIC_NPHASE), "pic_get_timing")
         return {name: (ms[i], cnt[i]) for i, name in enumerate(L.PHASES)}
+
+    def straggler_count(self) -> int:
+        """Particles the last fused launch sent to the HBM path (synchronises)."""
+        n = ctypes.c_int64()
+        self._call(self.lib.pic_straggler_count(self.ctx, ctypes.byref(n), ctypes.c_void_p(_stream())),
+                   "pic_straggler_count")
+        return int(n.value)
 
     @property
     def step_count(self) -> int:

@@ -17,7 +17,7 @@ def lib():
 
 
 def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec=L.PIC_FP32, tile=(8, 8, 8),
-           slack=1, sort_every=4, maxp=1000):
+           slack=1, sort_every=4, maxp=1000, acc=L.PIC_ACC_AUTO):
     p = L.Params()
     p.dims = dims
     p.n = L._c3i(*n)
@@ -29,6 +29,7 @@ def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec
     p.slack = slack
     p.sort_every = sort_every
     p.max_particles = maxp
+    p.current_accum = acc
     return p
 
 
@@ -57,8 +58,9 @@ def test_valid_init_and_queries(lib):
     bits = (ctypes.c_int32 * 3)()
     lib.pic_cell_bits(ctx, bits)
     assert tuple(bits) == (4, 4, 4)
-    # LDS: fields (8+1+2+2)^3 * 6 + current (8+2+3+2)^3 * 3, FP32
-    assert lib.pic_tile_lds_bytes(ctx) == (13 ** 3 * 6 + 15 ** 3 * 3) * 4
+    # LDS: fields (8+1+2+2)^3 * 6 in FP32 + current (8+2+3+2)^3 * 3 accumulated in FP64
+    # + a list of 512 wide-window particles (8 FP32 values + one int each) and its length
+    assert lib.pic_tile_lds_bytes(ctx) == 13 ** 3 * 6 * 4 + 15 ** 3 * 3 * 8 + 512 * 36 + 16
     assert lib.pic_step_count(ctx) == 0
     lib.pic_destroy(ctx)
 
@@ -75,7 +77,9 @@ def test_cfl_limit(lib, cfl, want):
     dict(dims=4), dict(order=3), dict(prec=7), dict(tile=(5, 8, 8)), dict(tile=(8, 8, 0)),
     dict(n=(16, 16, 2)), dict(dims=2, n=(16, 16, 4), tile=(8, 8, 1)), dict(dims=2, n=(16, 16, 1), tile=(8, 8, 2)),
     dict(sort_every=0), dict(slack=5), dict(maxp=-1), dict(dx=(0.05, 0.0, 0.05)),
+    dict(n=(64, 64, 64), tile=(32, 8, 8)),  # local cells must fit the packed 6-bit range
     dict(prec=L.PIC_FP64, tile=(16, 16, 16), n=(32, 32, 32)),  # LDS tile beyond 160 KB
+    dict(acc=3), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32),
 ])
 def test_invalid_params(lib, kw):
     st, ctx = init(lib, params(**kw))

@@ -260,3 +260,53 @@ def test_non_finite_particle_is_flagged_and_frozen():
     compare_species(g, "fp64", rest, ref_sp, "nan neighbours")
     compare_fields("fp64", s.get_fields(), ref_f, keys=("J",), what="nan neighbours")
     s.close()
+
+
+@pytest.mark.parametrize("dims,order", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_step_fused_fp32_lds_accumulation(dims, order):
+    """The FP32 state with the current tile accumulated in FP32 (the default is FP64)."""
+    from paper_1503_02464_amd.sim import Simulation
+    g = small_grid(dims, order)
+    sp, f = state(g, "fp32", 3, 0.3, 0.2, seed=100 + dims + order)
+    s = Simulation(g.dims, g.n, g.dx, g.dt, g.order, "fp32", tile=tiles(dims), slack=1, sort_every=4,
+                   max_particles=sp["w"].shape[0], current_accum="fp32")
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    O.step(g, ref_f, [ref_sp])
+    compare_species(g, "fp32", s.get_species(h), ref_sp, "fp32 accumulation")
+    compare_fields("fp32", s.get_fields(), ref_f, what="fp32 accumulation")
+    s.close()
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_sort_levels_spread_nodes(order):
+    """Inside a tile the sort lays particles out level by level, so a 64-lane
+    window rarely holds two particles with the same nearest node (cell for the
+    linear shape), whatever order they came in (here: cell by cell)."""
+    g = grid(3, (16, 16, 16), dx=0.05, cfl=0.7, order=order)
+    sp = inputs.uniform_plasma(g.n, 3, 8, 0.05, 1.0, seed=110)  # 8 per cell, cell by cell
+    tile = (8, 8, 8)
+    s = make_sim(g, "fp32", tile, max_particles=sp["w"].shape[0])
+    h = s.add_species(sp)
+    s.sort(h)
+    out = s.get_species(h)
+    start = s.tile_start(h)
+    node = out["cell"].astype(np.int64).copy()
+    if order == 2:
+        node = (node + (out["off"] >= 0.5)) % np.array(g.n)[:, None]
+    key = node[0] + g.n[0] * (node[1] + g.n[1] * node[2])
+    dup = total = 0
+    for t in range(len(start) - 1):
+        for b in range(start[t], start[t + 1], 64):
+            k = key[b:min(b + 64, start[t + 1])]
+            dup += k.size - np.unique(k).size
+            total += k.size
+    assert dup <= 0.05 * total, (dup, total)
+    # the unsorted input has 7 duplicates in every 8
+    k0 = (sp["cell"][0] + g.n[0] * (sp["cell"][1] + g.n[1] * sp["cell"][2]))[:4096]
+    assert sum(k0[i:i + 64].size - np.unique(k0[i:i + 64]).size for i in range(0, 4096, 64)) > 0.8 * 4096
+    s.close()
