@@ -128,6 +128,14 @@ typedef struct {
     int32_t sorted;      /* set to 1 by pic_sort; the caller sets 0 after it edits particles */
 } pic_species;
 
+/* Adjoint (reverse-mode) values of one species: one value per particle and
+ * component, in the species' precision.  x[d] is dL/d(position along d in
+ * cell units) (x[2] unused in 2D), u[d] is dL/du_d. */
+typedef struct {
+    void *x[3];
+    void *u[3];
+} pic_species_adjoint;
+
 typedef struct pic_ctx pic_ctx;
 
 /* Validate the parameters and create a context (host memory only).
@@ -184,6 +192,28 @@ pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields 
 #define PIC_NDIAG 8
 pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
                            double *out_host, void *stream);
+
+/* ---- Reverse mode (adjoint) of one step, for gradients of a loss of the
+ * final fields through K steps (the discrete adjoint of steps 1-4 above).
+ *
+ * pic_energy_adjoint: lam.E = scale dV E, lam.B = scale dV B (the gradient of
+ * scale * (U_E + U_B)); lam.J is not touched.
+ *
+ * pic_yee_adjoint: maps (lam.E, lam.B) of E^{n+1}, B^{n+1} to those of E^n,
+ * B^n through the Yee update (the transpose of pic_yee_step, using
+ * C_B = C_E^T), and writes lam.J = dL/dJ^{n+1/2} = -dt (lam.E after the first
+ * half).  Call it first for a step.
+ *
+ * pic_particle_adjoint: for one species given its state at step n (positions
+ * x^n, momenta u^{n-1/2}, in the same order as in the forward step, so the
+ * rollout must not re-sort between the two) and the fields E^n, B^n: reads
+ * lam.J and lsp (dL/dx^{n+1}, dL/du^{n+1/2}), replaces lsp by dL/dx^n,
+ * dL/du^{n-1/2}, and adds the transpose of the gather to lam.E and lam.B.
+ * Call it after pic_yee_adjoint of the same step, once per species. */
+pic_status pic_energy_adjoint(pic_ctx *ctx, const pic_fields *f, pic_fields *lam, double scale, void *stream);
+pic_status pic_yee_adjoint(pic_ctx *ctx, pic_fields *lam, void *stream);
+pic_status pic_particle_adjoint(pic_ctx *ctx, const pic_species *state, const pic_fields *f, pic_fields *lam,
+                                pic_species_adjoint *lsp, void *stream);
 
 /* Synchronise and report sticky device flags (PIC_ECROSS), then clear them. */
 pic_status pic_check(pic_ctx *ctx, void *stream);

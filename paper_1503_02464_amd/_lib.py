@@ -61,6 +61,10 @@ class Species(ctypes.Structure):
     ]
 
 
+class SpeciesAdjoint(ctypes.Structure):
+    _fields_ = [("x", _c3p), ("u", _c3p)]
+
+
 class PicError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"pic status {status}: {msg}")
@@ -102,6 +106,9 @@ def load(path: str = LIB_PATH):
         "pic_get_timing": (st, [ctx, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]),
         "pic_step_count": (ctypes.c_int64, [ctx]),
         "pic_straggler_count": (st, [ctx, P(ctypes.c_int64), ctypes.c_void_p]),
+        "pic_energy_adjoint": (st, [ctx, P(Fields), P(Fields), ctypes.c_double, ctypes.c_void_p]),
+        "pic_yee_adjoint": (st, [ctx, P(Fields), ctypes.c_void_p]),
+        "pic_particle_adjoint": (st, [ctx, P(Species), P(Fields), P(Fields), P(SpeciesAdjoint), ctypes.c_void_p]),
         "pic_last_error": (ctypes.c_char_p, [ctx]),
         "pic_status_string": (ctypes.c_char_p, [st]),
     }

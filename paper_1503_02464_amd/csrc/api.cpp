@@ -396,6 +396,46 @@ pic_status pic_diagnostics(pic_ctx *c, const pic_species *sp, int32_t nspecies, 
   return pic_check(c, stream);
 }
 
+pic_status pic_energy_adjoint(pic_ctx *c, const pic_fields *f, pic_fields *lam, double scale, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!fields_ok(f) || !fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
+  double dV = 1.0;
+  for (int d = 0; d < c->p.dims; ++d) dV *= c->p.dx[d];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pic::launch_scale_copy(*c, lam->E, f->E, scale * dV, s);
+  if (e == hipSuccess) e = pic::launch_scale_copy(*c, lam->B, f->B, scale * dV, s);
+  if (e != hipSuccess) return hip_fail(c, e, "energy_adjoint");
+  return PIC_OK;
+}
+
+pic_status pic_yee_adjoint(pic_ctx *c, pic_fields *lam, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pic::launch_yee_e(*c, *lam, s, -0.5, false);  // lamE -= dt/2 C_B lamB
+  if (e == hipSuccess) e = pic::launch_scale_copy(*c, lam->J, lam->E, -c->p.dt, s);  // lamJ = -dt lamE
+  if (e == hipSuccess) e = pic::launch_yee_b(*c, *lam, -1.0, s);  // lamB += dt C_E lamE
+  if (e == hipSuccess) e = pic::launch_yee_e(*c, *lam, s, -0.5, false);  // lamE -= dt/2 C_B lamB
+  if (e != hipSuccess) return hip_fail(c, e, "yee_adjoint");
+  return PIC_OK;
+}
+
+pic_status pic_particle_adjoint(pic_ctx *c, const pic_species *sp, const pic_fields *f, pic_fields *lam,
+                                pic_species_adjoint *lsp, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!species_ok(c, sp, false)) return fail(c, PIC_EINVAL, "bad species");
+  if (!fields_ok(f) || !fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
+  if (!lsp) return fail(c, PIC_EINVAL, "bad adjoint species");
+  if (sp->np > 0) {
+    for (int d = 0; d < 3; ++d)
+      if (!lsp->u[d] || (d < c->p.dims && !lsp->x[d])) return fail(c, PIC_EINVAL, "bad adjoint species");
+  }
+  hipError_t e = pic::launch_particle_adjoint(*c, *sp, *f, *lam, *lsp, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "particle_adjoint");
+  return PIC_OK;
+}
+
 pic_status pic_check(pic_ctx *c, void *stream) {
   if (!c) return PIC_EINVAL;
   if (pic_status s = check_ws(c)) return s;

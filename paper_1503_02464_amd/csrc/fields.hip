@@ -19,6 +19,7 @@ struct Yee {
   int n[3];
   T cx, cy, cz;  // dt/dx_d (times the half-step fraction for B)
   T cj;          // dt
+  int use_j;     // 0: E += frac dt curl B only (J is not read)
 };
 
 // B -= f dt curl E, forward differences onto the B points.
@@ -64,9 +65,12 @@ __global__ void __launch_bounds__(256) k_yee_e(Yee<T> a) {
     dBy_dz = a.cz * (by - a.Bi[1][km]);
     dBx_dz = a.cz * (bx - a.Bi[0][km]);
   }
-  a.Eo[0][o] += (dBz_dy - dBy_dz) - a.cj * a.J[0][o];
-  a.Eo[1][o] += (dBx_dz - dBz_dx) - a.cj * a.J[1][o];
-  a.Eo[2][o] += (dBy_dx - dBx_dy) - a.cj * a.J[2][o];
+  const T jx = a.use_j ? a.cj * a.J[0][o] : T(0);
+  const T jy = a.use_j ? a.cj * a.J[1][o] : T(0);
+  const T jz = a.use_j ? a.cj * a.J[2][o] : T(0);
+  a.Eo[0][o] += (dBz_dy - dBy_dz) - jx;
+  a.Eo[1][o] += (dBx_dz - dBz_dx) - jy;
+  a.Eo[2][o] += (dBy_dx - dBx_dy) - jz;
 }
 
 template <typename T>
@@ -90,6 +94,7 @@ Yee<T> yee_args(const pic_ctx &c, const pic_fields &f, double frac) {
   a.cy = static_cast<T>(frac * c.p.dt / c.p.dx[1]);
   a.cz = static_cast<T>(c.p.dims == 3 ? frac * c.p.dt / c.p.dx[2] : 0.0);
   a.cj = static_cast<T>(c.p.dt);
+  a.use_j = 1;
   return a;
 }
 
@@ -120,20 +125,24 @@ hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s) {
+hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s, double frac, bool with_j) {
   const int bs = yee_block(c);
   const dim3 grid = yee_grid(c, bs);
   const bool f64 = c.p.precision == PIC_FP64;
   if (f64) {
+    auto a = yee_args<double>(c, f, frac);
+    a.use_j = with_j ? 1 : 0;
     if (c.p.dims == 3)
-      hipLaunchKernelGGL((k_yee_e<double, 3>), grid, dim3(bs), 0, s, yee_args<double>(c, f, 1.0));
+      hipLaunchKernelGGL((k_yee_e<double, 3>), grid, dim3(bs), 0, s, a);
     else
-      hipLaunchKernelGGL((k_yee_e<double, 2>), grid, dim3(bs), 0, s, yee_args<double>(c, f, 1.0));
+      hipLaunchKernelGGL((k_yee_e<double, 2>), grid, dim3(bs), 0, s, a);
   } else {
+    auto a = yee_args<float>(c, f, frac);
+    a.use_j = with_j ? 1 : 0;
     if (c.p.dims == 3)
-      hipLaunchKernelGGL((k_yee_e<float, 3>), grid, dim3(bs), 0, s, yee_args<float>(c, f, 1.0));
+      hipLaunchKernelGGL((k_yee_e<float, 3>), grid, dim3(bs), 0, s, a);
     else
-      hipLaunchKernelGGL((k_yee_e<float, 2>), grid, dim3(bs), 0, s, yee_args<float>(c, f, 1.0));
+      hipLaunchKernelGGL((k_yee_e<float, 2>), grid, dim3(bs), 0, s, a);
   }
   return hipGetLastError();
 }

@@ -102,7 +102,13 @@ hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fie
 hipError_t launch_push_deposit_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s);
-hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s);
+// E += frac dt curl B (- dt J when with_j)
+hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s, double frac = 1.0, bool with_j = true);
+// Adjoint kernels.
+hipError_t launch_scale_copy(const pic_ctx &c, void *const dst[3], const void *const src[3], double scale,
+                             hipStream_t s);
+hipError_t launch_particle_adjoint(const pic_ctx &c, const pic_species &sp, const pic_fields &f,
+                                   const pic_fields &lam, const pic_species_adjoint &lsp, hipStream_t s);
 hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s);
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();
