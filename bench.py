@@ -12,7 +12,9 @@ update.  value = particle pushes per second over the timed steps.
 Also printed, in the same JSON line:
 * roofline: algorithmic bytes of the fused particle kernel per launch over its
   average launch time (HIP events on the launch stream, inside this run),
-  against the 8 TB/s HBM peak;
+  against the 8 TB/s HBM peak; traffic = HBM bytes per launch from the
+  FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ (null once the
+  kernel sources differ from the ones they were taken on);
 * cpu_baseline: the FP64 CPU oracle, one thread, one step of a 64^3 box of
   the same workload;
 * fp64: the same step in FP64 (value and roofline).
@@ -30,10 +32,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SORT_EVERY = 4
-# cells per tile and guard slack of the fused kernel, per precision (the FP64
-# tile is halved in z so fields + current fit the 160 KB of LDS)
-TILE = {"fp32": ((8, 8, 8), 1), "fp64": ((8, 8, 4), 1)}
 
 
 def particle_bytes(prec: str, dims: int) -> int:
@@ -56,6 +54,31 @@ def yee_cell_bytes(prec: str) -> int:
     return 15 * e
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_push_deposit_thermal3d_256c_8ppc.json")
+
+
+def measured_traffic(w, prec: str):
+    """HBM bytes per launch of the fused kernel from the FETCH_SIZE and
+    WRITE_SIZE counters (scaled by a plain copy of known size), if they were
+    taken on this workload, precision and the current kernel sources; else None."""
+    import hashlib
+    if prec != "fp32" or w.n != (256, 256, 256):
+        return None
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            prof = json.load(f)
+        h = hashlib.sha256()
+        for rel in prof["sources"]:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                h.update(f.read())
+    except (OSError, KeyError, ValueError):
+        return None
+    if h.hexdigest() != prof["sha256"]:
+        log("fused kernel sources changed since the traffic counters were taken: traffic = null")
+        return None
+    return int(prof["traffic_bytes_per_launch"])
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -70,9 +93,10 @@ def build_sim(w, prec: str, scale_note: str = ""):
     t0 = time.time()
     sp = inputs.uniform_plasma(w.n, w.dims, w.ppc, w.u_sigma, w.weight, w.seed)
     log(f"generated {sp['w'].shape[0]} particles in {time.time() - t0:.1f}s {scale_note}")
-    tile, slack = TILE[prec]
-    sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, prec, tile=tile, slack=slack, sort_every=SORT_EVERY,
-                     max_particles=sp["w"].shape[0])
+    from paper_1503_02464_amd.configs import BENCH_LAUNCH
+    lc = BENCH_LAUNCH[prec]
+    sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, prec, tile=lc["tile"], slack=lc["slack"],
+                     sort_every=lc["sort_every"], max_particles=sp["w"].shape[0])
     h = sim.add_species(sp)
     del sp
     torch.cuda.synchronize()
@@ -127,7 +151,7 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(w, prec),
             "bytes_per_launch": per_launch_bytes,
         },
         "yee_cell_updates_per_s": w.ncells / yee_avg_s,
@@ -136,13 +160,59 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
     }
 
 
+def adjoint_timing(prec: str = "fp32") -> dict:
+    """The differentiable 2D3V rollout at its full size (512^2 cells, 16 ppc,
+    linear shape, 200 steps, checkpoint every 20): forward and backward time."""
+    import numpy as np
+    import torch
+
+    from paper_1503_02464_amd import inputs
+    from paper_1503_02464_amd.autograd import Rollout, rollout_loss
+    from paper_1503_02464_amd.configs import diff_2d
+
+    w = diff_2d()
+    sp = inputs.uniform_plasma(w.n, 2, w.ppc, w.u_sigma, w.weight, w.seed)
+    src = inputs.rng(w.seed + 1).normal(0, w.extra["src_sigma"], w.ncells)
+    roll = Rollout(2, w.n, w.dx, w.dt, w.order, prec, sp, w.steps, w.extra["checkpoint_every"])
+    s = torch.tensor(src, dtype=torch.float64, device="cuda", requires_grad=True)
+    u0 = torch.tensor(sp["u"], dtype=torch.float64, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = rollout_loss(roll, s, u0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    npart = sp["w"].shape[0]
+    roll.sim.close()
+    log(f"adjoint rollout: forward {t1 - t0:.2f}s backward {t2 - t1:.2f}s")
+    return {"workload": w.name, "particles": npart, "steps": w.steps, "checkpoint_every": w.extra["checkpoint_every"],
+            "precision": prec, "forward_ms_per_step": (t1 - t0) / w.steps * 1e3,
+            "backward_ms_per_step": (t2 - t1) / w.steps * 1e3,
+            "backward_over_forward": (t2 - t1) / (t1 - t0), "loss": float(L.item()),
+            "grad_norm_src": float(s.grad.norm().item()), "grad_norm_u0": float(u0.grad.norm().item())}
+
+
+def copy_probe(nbytes: int = 1 << 30) -> None:
+    """One plain device-to-device copy of nbytes (twice), to calibrate the
+    FETCH_SIZE / WRITE_SIZE counters against a kernel of known traffic."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy probe: {nbytes} bytes read and written per copy")
+
+
 def cpu_baseline(w) -> dict:
     """The FP64 oracle, one thread, one step of a 64^3 box of the same workload."""
     import oracle as O
     from paper_1503_02464_amd import inputs
-    from paper_1503_02464_amd.configs import c3_thermal_3d
+    from paper_1503_02464_amd.configs import thermal_3d
 
-    ws = c3_thermal_3d(scale=4)
+    ws = thermal_3d(scale=4)
     g = O.Grid(3, ws.n, ws.dx, ws.dt, ws.order)
     sp = inputs.uniform_plasma(ws.n, 3, ws.ppc, ws.u_sigma, ws.weight, ws.seed)
     f = O.new_fields(g)
@@ -163,6 +233,8 @@ def main() -> int:
     ap.add_argument("--scale", type=int, default=1, help="divide the 256^3 box by this per dimension (testing)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU spatial decomposition "
@@ -170,12 +242,15 @@ def main() -> int:
         return 2
     import torch
 
-    from paper_1503_02464_amd.configs import c3_thermal_3d
+    from paper_1503_02464_amd.configs import BENCH_LAUNCH, thermal_3d
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    w = c3_thermal_3d(scale=args.scale)
+    w = thermal_3d(scale=args.scale)
     res32 = run_precision(w, "fp32", args.steps, args.warmup)
     res64 = None if args.no_fp64 else run_precision(w, "fp64", args.steps, args.warmup)
+    adj = None if (args.no_adjoint or args.scale != 1) else adjoint_timing("fp32")
+    if args.copy_probe:
+        copy_probe()
     base = None if args.no_cpu_baseline else cpu_baseline(w)
     line = {
         "metric": "particle pushes/s (gather+Boris+deposit), FP32 vs FP64 at stated error; HBM %",
@@ -192,8 +267,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "cells": list(w.n), "particles": res32["particles"], "ppc": w.ppc,
                    "shape_order": w.order, "dx": w.dx[0], "dt": w.dt, "u_sigma": w.u_sigma,
-                   "tile": list(TILE["fp32"][0]), "slack": TILE["fp32"][1], "sort_every": SORT_EVERY,
-                   "positions": "int32 cell + f32 offset"},
+                   **{k: (list(v) if isinstance(v, tuple) else v) for k, v in BENCH_LAUNCH["fp32"].items()},
+                   "positions": "int32 cell + f32 offset", "lds_current": "f64"},
         "roofline": res32["roofline"],
         "cpu_baseline": base,
         "phases_ms_per_launch": res32["phases_ms_per_launch"],
@@ -202,6 +277,7 @@ def main() -> int:
         "fp64": None if res64 is None else {k: res64[k] for k in ("value", "ms_per_step", "roofline",
                                                                   "phases_ms_per_launch",
                                                                   "yee_cell_updates_per_s")},
+        "adjoint": adj,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -61,14 +61,14 @@ class Workload:
         return self.density * self.cell_volume / self.ppc
 
 
-def c1_small_2d() -> Workload:
+def uniform_2d_small() -> Workload:
     """2D3V periodic uniform plasma, 64x64, dx = 0.05, 0.7 CFL, 4 ppc, sigma 0.01,
     linear shape, 100 steps, FP64."""
     return Workload("uniform-2d3v-64x64-4ppc-linear", 2, (64, 64, 1), (0.05, 0.05, 1.0), 0.7, 1, 4, 0.01, 100,
                     seed=1000, tile=(8, 8, 1))
 
 
-def c3_thermal_3d(scale: int = 1) -> Workload:
+def thermal_3d(scale: int = 1) -> Workload:
     """3D3V periodic uniform thermal plasma, 256^3 (divided by ``scale`` per dim),
     8 ppc, sigma 0.05, quadratic shape, 200 steps; the bandwidth benchmark."""
     n = 256 // scale
@@ -76,10 +76,17 @@ def c3_thermal_3d(scale: int = 1) -> Workload:
                     seed=1002, tile=(8, 8, 8))
 
 
-def c5_diff_2d(n: int = 512) -> Workload:
+def diff_2d(n: int = 512) -> Workload:
     """Differentiable 2D3V rollout: 512^2, 16 ppc, sigma 0.02, linear shape, 200 steps."""
     return Workload(f"diff-2d3v-{n}x{n}-16ppc-linear", 2, (n, n, 1), (0.05, 0.05, 1.0), 0.7, 1, 16, 0.02, 200,
                     seed=1004, tile=(16, 16, 1), extra={"checkpoint_every": 20, "src_sigma": 0.01})
 
 
-WORKLOADS = {"C1": c1_small_2d, "C3": c3_thermal_3d, "C5": c5_diff_2d}
+WORKLOADS = {"uniform-2d-64": uniform_2d_small, "thermal-3d-256": thermal_3d, "diff-2d-512": diff_2d}
+
+
+# Launch configuration of the fused step for the 3D benchmark workload, per
+# precision: cells per tile, guard slack, sort cadence.  The FP64 tile is
+# halved in z so fields + current + the wide-window list fit 160 KB of LDS.
+BENCH_LAUNCH = {"fp32": {"tile": (8, 8, 8), "slack": 1, "sort_every": 4},
+                "fp64": {"tile": (8, 8, 4), "slack": 1, "sort_every": 4}}

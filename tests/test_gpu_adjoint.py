@@ -96,8 +96,8 @@ def directional_fd(roll, src, u0, vs, vu, eps):
 
 
 def c5_like(n, ppc, steps):
-    from paper_1503_02464_amd.configs import c5_diff_2d
-    w = c5_diff_2d(n)
+    from paper_1503_02464_amd.configs import diff_2d
+    w = diff_2d(n)
     w.ppc = ppc
     g = grid(2, w.n[:2], dx=w.dx[0], cfl=w.cfl, order=w.order)
     sp = inputs.uniform_plasma(w.n, 2, ppc, w.u_sigma, w.density * w.cell_volume / ppc, w.seed)

@@ -127,8 +127,8 @@ def test_sort(prec, dims, order):
 
 def test_c1_100_steps_fp64():
     """The small 2D workload (64x64, 4 ppc, linear, 0.7 CFL) for 100 steps, FP64."""
-    from paper_1503_02464_amd.configs import c1_small_2d
-    w = c1_small_2d()
+    from paper_1503_02464_amd.configs import uniform_2d_small
+    w = uniform_2d_small()
     g = grid(2, w.n[:2], dx=w.dx[0], cfl=w.cfl, order=w.order)
     sp = inputs.uniform_plasma(w.n, 2, w.ppc, w.u_sigma, w.weight, w.seed)
     from gpu_helpers import unique_weights
