@@ -78,6 +78,12 @@ def _bind(path: str):
     lib.or_yee_b.argtypes = [g, ctypes.c_double] + [_D] * 6
     lib.or_yee_e.argtypes = [g] + [_D] * 9
     lib.or_yee_step.argtypes = [g] + [_D] * 9
+    lib.or_yee_step_open.argtypes = [g] + [_D] * 9
+    lib.or_laser_j0.argtypes = [g, ctypes.c_double, ctypes.c_double]
+    lib.or_laser_j0.restype = ctypes.c_double
+    lib.or_laser_add.argtypes = [g, _D, _D, ctypes.c_int32, ctypes.c_int32] + [ctypes.c_double] * 8
+    lib.or_absorb.argtypes = [ctypes.c_int64, _I, ctypes.c_int32, ctypes.c_int32, _D]
+    lib.or_absorb.restype = ctypes.c_int64
     lib.or_rho.argtypes = [g, ctypes.c_double, ctypes.c_int64] + [_I] * 3 + [_D] * 3 + [_D, _D]
     lib.or_div.argtypes = [g] + [_D] * 4
     lib.or_field_energy.argtypes = [g] + [_D] * 3
@@ -252,6 +258,74 @@ def yee_step(grid: Grid, fields: dict) -> None:
     yee_b(grid, 0.5, fields["E"], fields["B"])
     yee_e(grid, fields["B"], fields["J"], fields["E"])
     yee_b(grid, 0.5, fields["E"], fields["B"])
+
+
+def yee_step_open(grid: Grid, fields: dict) -> None:
+    """The Yee step with open (first-order Mur) x faces, periodic y and z."""
+    E, B, J = fields["E"], fields["B"], fields["J"]
+    _load().or_yee_step_open(grid.c(), _d(E[0]), _d(E[1]), _d(E[2]), _d(B[0]), _d(B[1]), _d(B[2]),
+                             _d(J[0]), _d(J[1]), _d(J[2]))
+
+
+@dataclass
+class Laser:
+    """A laser current sheet on the node plane x = plane * dx (readings: see
+    or_laser_add).  pol 1 = E_y, 2 = E_z; w0 is the 1/e field radius, tau the
+    FWHM of the intensity envelope, t0 its centre, (yc, zc) the axis."""
+
+    plane: int
+    e0: float
+    omega: float = 1.0
+    w0: float = 1e30
+    tau: float = 1e30
+    t0: float = 0.0
+    yc: float = 0.0
+    zc: float = 0.0
+    pol: int = 1
+
+
+def laser_j0(grid: Grid, e0: float, omega: float) -> float:
+    return _load().or_laser_j0(grid.c(), e0, omega)
+
+
+def laser_add(grid: Grid, J: np.ndarray, laser: Laser, t: float) -> None:
+    _load().or_laser_add(grid.c(), _d(J[1]), _d(J[2]), laser.plane, laser.pol, laser.e0, laser.omega, laser.w0,
+                         laser.tau, laser.t0, laser.yc, laser.zc, t)
+
+
+def absorb(sp: dict, lo: int, hi: int) -> int:
+    """Mark particles whose x cell left [lo, hi) as removed (w = 0)."""
+    ix = np.ascontiguousarray(sp["cell"][0], np.int32)
+    return _load().or_absorb(sp["w"].shape[0], _i(ix), lo, hi, _d(sp["w"]))
+
+
+def compact(sp: dict) -> dict:
+    """Drop removed (w == 0) particles."""
+    keep = sp["w"] != 0.0
+    return {"q": sp["q"], "m": sp["m"], "cell": sp["cell"][:, keep].copy(), "off": sp["off"][:, keep].copy(),
+            "u": sp["u"][:, keep].copy(), "w": sp["w"][keep].copy()}
+
+
+def step_open(grid: Grid, fields: dict, species: list, lo: int, hi: int, laser: Laser | None = None,
+              n: int = 0) -> tuple:
+    """One step of a box with open x faces (step number n, J at t = (n + 1/2) dt):
+    J = 0; every species pushed and deposited; the laser sheet added; particles
+    whose x cell left [lo, hi) removed; the Yee step with Mur faces.  Returns
+    (species with the removed particles dropped, count of moves > 1 cell,
+    removed count)."""
+    fields["J"][...] = 0.0
+    bad = 0
+    for sp in species:
+        bad += push_deposit(grid, fields, sp)
+    if laser is not None:
+        laser_add(grid, fields["J"], laser, (n + 0.5) * grid.dt)
+    removed = 0
+    out = []
+    for sp in species:
+        removed += absorb(sp, lo, hi)
+        out.append(compact(sp))
+    yee_step_open(grid, fields)
+    return out, bad, removed
 
 
 def step(grid: Grid, fields: dict, species: list) -> int:

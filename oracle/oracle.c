@@ -423,6 +423,106 @@ void or_yee_step(const or_grid *g, double *Ex, double *Ey, double *Ez, double *B
 }
 
 /* ------------------------------------------------------------------ */
+/* Open x boundary and laser source.  The paper leaves boundaries and    */
+/* laser injection out (Sec. 2); the readings used here are:             */
+/*  - the x faces are the node planes i = 0 and i = n0-1; the tangential */
+/*    E components there (Ey, Ez) follow Mur's first-order one-way wave  */
+/*    condition (G. Mur, IEEE Trans. EMC 23 (1981) 377) instead of the   */
+/*    curl update; y and z stay periodic;                                */
+/*  - a particle whose cell leaves [lo, hi) along x after its move is    */
+/*    removed, after it has deposited that step's current;               */
+/*  - the laser is a sheet of current J_y (or J_z) on the node plane i_s */
+/*    whose amplitude makes the radiated plane wave of the discrete Yee  */
+/*    lattice, in the steady state, exactly E0 on both sides.            */
+/* ------------------------------------------------------------------ */
+
+/* One Yee step with open x faces: the periodic step, except that Ey and Ez
+ * on the planes i = 0 and i = n0-1 take E^{n+1}_face = E^n_next +
+ * a (E^{n+1}_next - E^n_face), a = (dt - dx)/(dt + dx), "next" being the
+ * plane one cell inside. */
+void or_yee_step_open(const or_grid *g, double *Ex, double *Ey, double *Ez, double *Bx, double *By,
+                      double *Bz, const double *Jx, const double *Jy, const double *Jz)
+{
+    const int64_t n0 = g->n[0], nyz = (int64_t)g->n[1] * g->n[2];
+    const int64_t planes[4] = {0, 1, n0 - 2, n0 - 1};
+    double *old = (double *)malloc(sizeof(double) * 2 * 4 * nyz);
+    or_yee_b(g, 0.5, Ex, Ey, Ez, Bx, By, Bz);
+    for (int64_t jk = 0; jk < nyz; ++jk)
+        for (int p = 0; p < 4; ++p) {
+            int64_t o = planes[p] + n0 * jk;
+            old[(0 * 4 + p) * nyz + jk] = Ey[o];
+            old[(1 * 4 + p) * nyz + jk] = Ez[o];
+        }
+    or_yee_e(g, Bx, By, Bz, Jx, Jy, Jz, Ex, Ey, Ez);
+    const double a = (g->dt - g->dx[0]) / (g->dt + g->dx[0]);
+    for (int64_t jk = 0; jk < nyz; ++jk) {
+        double *F[2] = {Ey, Ez};
+        for (int c = 0; c < 2; ++c) {
+            const double *o = old + c * 4 * nyz;
+            double *f = F[c];
+            /* low face: the wave leaves towards -x */
+            f[0 + n0 * jk] = o[1 * nyz + jk] + a * (f[1 + n0 * jk] - o[0 * nyz + jk]);
+            /* high face: the wave leaves towards +x */
+            f[(n0 - 1) + n0 * jk] = o[2 * nyz + jk] + a * (f[(n0 - 2) + n0 * jk] - o[3 * nyz + jk]);
+        }
+    }
+    or_yee_b(g, 0.5, Ex, Ey, Ez, Bx, By, Bz);
+    free(old);
+}
+
+/* Current-sheet amplitude that radiates a plane wave of amplitude e0 and
+ * angular frequency omega to both sides on the Yee lattice (normal
+ * incidence, dx = dx[0]).  From the discrete wave equation with a source
+ * J on one node plane: E = -J dx^2 sin(omega dt / 2) / (dt sin(k dx)),
+ * with sin(k dx / 2) = (dx / dt) sin(omega dt / 2). */
+double or_laser_j0(const or_grid *g, double e0, double omega)
+{
+    const double dx = g->dx[0], dt = g->dt;
+    const double s = sin(0.5 * omega * dt);
+    const double k = 2.0 * asin(dx / dt * s) / dx;
+    return -e0 * dt * sin(k * dx) / (dx * dx * s);
+}
+
+/* Add the laser sheet to J at time t (the J time level, n + 1/2):
+ * J_pol(i_s, y, z) += j0 f(y, z) g(t) sin(omega (t - t0)), with
+ * f = exp(-((y - yc)^2 + (z - zc)^2) / w0^2) (w0: 1/e field radius) and
+ * g = exp(-2 ln 2 (t - t0)^2 / tau^2) (tau: FWHM of the intensity).
+ * pol = 1 puts it on J_y (positions (i_s, j + 1/2, k)), pol = 2 on J_z
+ * (positions (i_s, j, k + 1/2)). */
+void or_laser_add(const or_grid *g, double *Jy, double *Jz, int32_t plane, int32_t pol, double e0,
+                  double omega, double w0, double tau, double t0, double yc, double zc, double t)
+{
+    const double j0 = or_laser_j0(g, e0, omega);
+    const double env = exp(-2.0 * log(2.0) * (t - t0) * (t - t0) / (tau * tau));
+    const double carrier = sin(omega * (t - t0));
+    for (int64_t k = 0; k < g->n[2]; ++k)
+        for (int64_t j = 0; j < g->n[1]; ++j) {
+            double y = ((double)j + (pol == 1 ? 0.5 : 0.0)) * g->dx[1];
+            double z = g->dims == 3 ? ((double)k + (pol == 2 ? 0.5 : 0.0)) * g->dx[2] : 0.0;
+            double r2 = (y - yc) * (y - yc) + (g->dims == 3 ? (z - zc) * (z - zc) : 0.0);
+            double v = j0 * exp(-r2 / (w0 * w0)) * env * carrier;
+            int64_t o = lin(g, plane, j, k);
+            if (pol == 1)
+                Jy[o] += v;
+            else
+                Jz[o] += v;
+        }
+}
+
+/* Mark every particle whose x cell is outside [lo, hi) as removed (weight
+ * set to 0); returns how many were marked. */
+int64_t or_absorb(int64_t np, const int32_t *ix, int32_t lo, int32_t hi, double *w)
+{
+    int64_t removed = 0;
+    for (int64_t p = 0; p < np; ++p)
+        if (w[p] != 0.0 && (ix[p] < lo || ix[p] >= hi)) {
+            w[p] = 0.0;
+            ++removed;
+        }
+    return removed;
+}
+
+/* ------------------------------------------------------------------ */
 /* Diagnostics.                                                          */
 /* ------------------------------------------------------------------ */
 

@@ -515,6 +515,170 @@ def pin_translation_invariance(dims=3, order=2):
     assert np.array_equal(sp["off"], sp2["off"]) and np.array_equal(sp["u"], sp2["u"])
 
 
+# ------------------------------------------------------------------ open x boundary, laser, absorption
+
+def _mur_r(k, omega, dx, dt):
+    """Reflection coefficient of first-order Mur at normal incidence on the
+    Yee lattice, from E_i^n = Z^n (P^-i + R P^i) (Z = e^{-i w dt}, P = e^{i k dx},
+    the face at i = 0) substituted into the face update."""
+    a = (dt - dx) / (dt + dx)
+    Z = np.exp(-1j * omega * dt)
+    P = np.exp(1j * k * dx)
+    return (1 / P + a * Z / P - a - Z) / (Z - P - a * Z * P + a)
+
+
+def _two_waves(g, k, omega, R, face, step):
+    """Exact lattice fields (E at step n, B^n = average of B^{n -/+ 1/2}) of a
+    unit wave travelling towards x-face ``face`` (0: low, 1: high) plus its
+    reflection R, both polarisations (E_y with B_z, E_z with B_y), uniform in y, z."""
+    n0 = g.n[0]
+    dx, dt = g.dx[0], g.dt
+    m = 0 if face == 0 else n0 - 1
+    sgn_in = -1.0 if face == 0 else 1.0
+    i = np.arange(n0)
+    t = step * dt
+    Ey = np.zeros(n0, complex)
+    Bz = np.zeros(n0, complex)
+    for amp, kappa in ((1.0, sgn_in * k), (R, -sgn_in * k)):
+        # B-hat / E-hat = (dt/dx) sin(kappa dx/2) / sin(omega dt/2): +1 for kappa > 0
+        ratio = dt / dx * math.sin(kappa * dx / 2) / math.sin(omega * dt / 2)
+        Ey += amp * np.exp(1j * (kappa * (i - m) * dx - omega * t))
+        Bz += amp * ratio * math.cos(omega * dt / 2) * np.exp(1j * (kappa * (i + 0.5 - m) * dx - omega * t))
+    E = np.zeros((3, g.ncells))
+    B = np.zeros((3, g.ncells))
+    reps = g.ncells // n0
+    E[1] = np.tile(Ey.real, reps)
+    B[2] = np.tile(Bz.real, reps)
+    # the E_z wave: dB_y/dt = +dE_z/dx, so B_y carries the opposite sign
+    E[2] = np.tile((0.5 * Ey).imag, reps)
+    B[1] = -np.tile((0.5 * Bz).imag, reps)
+    return E, B
+
+
+def pin_mur_exact_reflection(dims=2):
+    """A lattice plane wave meeting an open face plus its reflection with the
+    closed-form Mur coefficient R is an exact solution: one oracle step of it
+    reproduces the superposition at the next step to round-off, face nodes
+    included (Mur 1981, on the Yee lattice)."""
+    n = (40, 4, 3)[:dims]
+    g = grid(dims, n, dx=0.1, cfl=0.8)
+    dx, dt = g.dx[0], g.dt
+    k = 2 * math.pi / (16 * dx)
+    omega = 2 / dt * math.asin(dt / dx * math.sin(k * dx / 2))
+    R = _mur_r(k, omega, dx, dt)
+    assert 0.0 < abs(R) < 0.05, abs(R)
+    n0 = g.n[0]
+    for face in (0, 1):
+        E, B = _two_waves(g, k, omega, R, face, 7)
+        f = {"E": E.copy(), "B": B.copy(), "J": np.zeros_like(E)}
+        O.yee_step_open(g, f)
+        E1, B1 = _two_waves(g, k, omega, R, face, 8)
+        # exact where nothing from the other face (or the wrap) reaches in one step
+        ie = np.arange(0, n0 - 1) if face == 0 else np.arange(1, n0)
+        ib = np.arange(0, n0 - 2) if face == 0 else np.arange(1, n0 - 1)
+        sel_e = np.isin(np.arange(g.ncells) % n0, ie)
+        sel_b = np.isin(np.arange(g.ncells) % n0, ib)
+        for c in (1, 2):
+            assert np.max(np.abs(f["E"][c][sel_e] - E1[c][sel_e])) < 1e-13, (face, c)
+        for c in (1, 2):
+            assert np.max(np.abs(f["B"][c][sel_b] - B1[c][sel_b])) < 1e-13, (face, c)
+        # and without the reflected part the face update is wrong: the pin sees R
+        E0, B0 = _two_waves(g, k, omega, 0.0, face, 7)
+        f0 = {"E": E0, "B": B0, "J": np.zeros_like(E0)}
+        O.yee_step_open(g, f0)
+        E10, _ = _two_waves(g, k, omega, 0.0, face, 8)
+        m = 0 if face == 0 else n0 - 1
+        face_sel = np.arange(g.ncells) % n0 == m
+        assert np.max(np.abs(f0["E"][1][face_sel] - E10[1][face_sel])) > 0.2 * abs(R)
+
+
+def pin_laser_plane_wave():
+    """The laser sheet with a long envelope radiates E_y = E0 g sin(w(t - t0) - k|x - xs|)
+    to both sides, k the lattice wavenumber of w (steady-state amplitude of a
+    current sheet on the Yee lattice)."""
+    lam = 2 * math.pi
+    g = grid(2, (4000, 2), dx=lam / 40, cfl=0.98)
+    n0 = g.n[0]
+    xs = n0 // 2
+    tau = 40 * lam
+    t0 = 12 * lam
+    las = O.Laser(plane=xs, e0=0.7, omega=1.0, tau=tau, t0=t0, pol=1)
+    f = O.new_fields(g)
+    steps = int(round((t0 + 0.3 * lam) / g.dt))
+    for n in range(steps):
+        f["J"][...] = 0.0
+        O.laser_add(g, f["J"], las, (n + 0.5) * g.dt)
+        O.yee_step_open(g, f)
+    t = steps * g.dt
+    dx = g.dx[0]
+    k = 2 * math.asin(dx / g.dt * math.sin(0.5 * g.dt)) / dx
+    d = np.arange(-120, 121)
+    i = xs + d
+    x = np.abs(d) * dx
+    env = np.exp(-2 * math.log(2) * (t - x - t0) ** 2 / tau ** 2)
+    ref = las.e0 * env * np.sin((t - t0) - k * x)
+    got = f["E"][1][i]  # row j = 0
+    assert np.max(np.abs(got - ref)) < 3e-3 * las.e0, np.max(np.abs(got - ref))
+    # a beam axis on a J_y point (y = (j + 1/2) dy) gives a sheet symmetric about that row
+    g3 = grid(2, (8, 16), dx=0.1, cfl=0.5)
+    jc = 7
+    beam = O.Laser(plane=3, e0=1.0, w0=0.35, tau=5.0, t0=0.0, yc=(jc + 0.5) * g3.dx[1], pol=1)
+    J = np.zeros((3, g3.ncells))
+    O.laser_add(g3, J, beam, 0.9)
+    row = J[1].reshape(g3.n[1], g3.n[0])[:, 3]
+    m = np.arange(1, 7)
+    assert np.max(np.abs(row[jc + m] - row[jc - m])) < 1e-14 * np.max(np.abs(row)) and np.max(np.abs(row)) > 0
+    assert np.argmax(np.abs(row)) == jc
+
+
+def pin_absorption_gauss():
+    """Removing the particles whose x cell leaves [lo, hi) changes Gauss's
+    residual D.E - rho by exactly the removed charge density (interior nodes),
+    since Esirkepov + Yee keep it fixed for the particles that stay; each
+    particle leaves in the step its straight orbit predicts."""
+    g = grid(2, (32, 8), dx=0.1, cfl=0.6, order=2)
+    lo, hi = 6, 26
+    r = np.random.default_rng(5)
+    npart = 40
+    cell = np.zeros((3, npart), np.int32)
+    cell[0] = r.integers(lo, lo + 3, npart)
+    cell[1] = r.integers(0, 8, npart)
+    off = np.zeros((3, npart))
+    off[:2] = r.random((2, npart))
+    u = np.zeros((3, npart))
+    u[0] = -r.uniform(0.2, 0.9, npart)  # towards the low face, no fields: straight lines
+    u[1] = r.normal(0, 0.1, npart)
+    # tiny weights: the self-fields stay far too weak to bend the orbits in 12 steps
+    sp = {"q": -1.0, "m": 1.0, "cell": cell, "off": off, "u": u, "w": r.uniform(0.5, 1.5, npart) * 1e-6}
+    x0 = cell[0] + off[0]
+    gam = np.sqrt(1 + np.sum(u * u, axis=0))
+    vx = u[0] / gam * g.dt / g.dx[0]  # cells per step
+    f = O.new_fields(g)
+    G = lambda spl: O.div(g, f["E"]) - O.rho(g, spl)
+    left = np.ones(npart, bool)
+    interior = (np.arange(g.ncells) % g.n[0] >= 2) & (np.arange(g.ncells) % g.n[0] <= g.n[0] - 3)
+    for n in range(12):
+        g0 = G([sp])
+        before = O.copy_species(sp)
+        f_before = {k: v.copy() for k, v in f.items()}
+        out, bad, removed = O.step_open(g, f, [sp], lo, hi)
+        assert bad == 0
+        gone = np.isin(before["w"], out[0]["w"], invert=True)
+        # removed particles at their new positions (the same push), with their weights
+        moved = O.copy_species(before)
+        O.push_deposit(g, f_before, moved)
+        rem = {k: (v[..., gone] if isinstance(v, np.ndarray) else v) for k, v in moved.items()}
+        dG = G(out) - g0
+        expect = O.rho(g, [rem]) if gone.any() else np.zeros(g.ncells)
+        scale = np.max(np.abs(O.rho(g, [before])))
+        assert np.max(np.abs((dG - expect)[interior])) < 1e-12 * scale, n
+        # removal step from the straight orbit: floor(x0 + (n+1) vx) < lo
+        pred = np.floor(x0 + (n + 1) * vx) < lo
+        assert removed == int(np.sum(pred & left)), (n, removed, int(np.sum(pred & left)))
+        left &= ~pred
+        sp = out[0]
+
+
 ALL_PINS = [
     pin_shape_values, pin_shape_moments,
     lambda: pin_gather_uniform(3, 2), lambda: pin_gather_uniform(2, 1),
@@ -532,4 +696,6 @@ ALL_PINS = [
     pin_plasma_frequency,
     lambda: pin_gauss_conserved(3, 2), lambda: pin_gauss_conserved(2, 1),
     lambda: pin_translation_invariance(3, 2), lambda: pin_translation_invariance(2, 1),
+    lambda: pin_mur_exact_reflection(2), lambda: pin_mur_exact_reflection(3), pin_laser_plane_wave,
+    pin_absorption_gauss,
 ]

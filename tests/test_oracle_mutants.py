@@ -39,6 +39,17 @@ MUTANTS = [
     ("yee_e_current_sign", "Ex[o] += c * ((dBz_dy - dBy_dz) - Jx[o]);", "Ex[o] += c * ((dBz_dy - dBy_dz) + Jx[o]);"),
     ("yee_e_forward_difference", "double dBz_dy = (Bz[o] - Bz[lin(g, i, j - 1, k)]) / g->dx[1];",
      "double dBz_dy = (Bz[lin(g, i, j + 1, k)] - Bz[o]) / g->dx[1];"),
+    ("mur_coefficient_sign", "const double a = (g->dt - g->dx[0]) / (g->dt + g->dx[0]);",
+     "const double a = (g->dx[0] - g->dt) / (g->dt + g->dx[0]);"),
+    ("mur_low_planes", "f[0 + n0 * jk] = o[1 * nyz + jk] + a * (f[1 + n0 * jk] - o[0 * nyz + jk]);",
+     "f[0 + n0 * jk] = o[0 * nyz + jk] + a * (f[1 + n0 * jk] - o[1 * nyz + jk]);"),
+    ("mur_high_planes", "o[2 * nyz + jk] + a * (f[(n0 - 2) + n0 * jk] - o[3 * nyz + jk]);",
+     "o[3 * nyz + jk] + a * (f[(n0 - 2) + n0 * jk] - o[2 * nyz + jk]);"),
+    ("laser_sheet_factor", "return -e0 * dt * sin(k * dx) / (dx * dx * s);",
+     "return -e0 * dt * sin(0.5 * k * dx) / (dx * dx * s);"),
+    ("laser_sign", "return -e0 * dt * sin(k * dx) / (dx * dx * s);", "return e0 * dt * sin(k * dx) / (dx * dx * s);"),
+    ("laser_stagger", "double y = ((double)j + (pol == 1 ? 0.5 : 0.0)) * g->dx[1];", "double y = (double)j * g->dx[1];"),
+    ("absorb_edge", "(ix[p] < lo || ix[p] >= hi)", "(ix[p] <= lo || ix[p] >= hi)"),
     ("rho_volume", "+= q * w[p] / dV * (wx * wy * wz);", "+= q * w[p] * (wx * wy * wz);"),
     ("div_stagger", "double d = (Fx[o] - Fx[lin(g, i - 1, j, k)]) / g->dx[0]",
      "double d = (Fx[lin(g, i + 1, j, k)] - Fx[o]) / g->dx[0]"),

@@ -16,6 +16,7 @@ IDS = [
     "x_only_q", "x_only_l", "jz_2d_q", "jz_2d_l", "jz_2d_time_average",
     "cold_k0_2d_l", "cold_k0_3d_q", "plasma_frequency",
     "gauss_3d_q", "gauss_2d_l", "translation_3d_q", "translation_2d_l",
+    "mur_reflection_2d", "mur_reflection_3d", "laser_plane_wave", "absorption_gauss",
 ]
 assert len(IDS) == len(pins.ALL_PINS)
 
