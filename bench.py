@@ -17,7 +17,9 @@ Also printed, in the same JSON line:
   kernel sources differ from the ones they were taken on);
 * cpu_baseline: the FP64 CPU oracle, one thread, one step of a 64^3 box of
   the same workload;
-* fp64: the same step in FP64 (value and roofline).
+* fp64: the same step in FP64 (value and roofline);
+* adjoint: forward and backward time of the differentiable 2D rollout;
+* laser_foil: time per step of the two laser-on-foil boxes (FP32).
 """
 from __future__ import annotations
 
@@ -194,6 +196,43 @@ def adjoint_timing(prec: str = "fp32") -> dict:
             "grad_norm_src": float(s.grad.norm().item()), "grad_norm_u0": float(u0.grad.norm().item())}
 
 
+def laser_foil_timing(w, steps: int, warmup: int) -> dict:
+    """A laser-on-foil box (open x faces, laser sheet, electrons + ions) in its
+    launch configuration, FP32: time per whole step and pushes per second of
+    both species.  Most tiles hold no particle, so this measures how little
+    the empty ones cost."""
+    import torch
+
+    from paper_1503_02464_amd.sim import Simulation
+
+    t0 = time.time()
+    e, i = w.species()
+    npart = e["w"].shape[0] + i["w"].shape[0]
+    sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, "fp32", tile=w.tile, slack=1, sort_every=4,
+                     max_particles=e["w"].shape[0], open_x=True, absorb=w.absorb)
+    sim.set_laser(**w.laser())
+    sim.add_species(e)
+    sim.add_species(i)
+    del e, i
+    log(f"{w.name}: set up {npart} particles in {time.time() - t0:.1f}s")
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.check()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    sim.check()
+    sim.set_timing(True)
+    sim.step(steps)
+    tim = sim.get_timing()
+    sim.set_timing(False)
+    sim.close()
+    return {"workload": w.name, "particles": npart, "cells": w.ncells, "steps": steps,
+            "ms_per_step": el / steps * 1e3, "pushes_per_s": npart * steps / el,
+            "phases_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in tim.items()}}
+
+
 def copy_probe(nbytes: int = 1 << 30) -> None:
     """One plain device-to-device copy of nbytes (twice), to calibrate the
     FETCH_SIZE / WRITE_SIZE counters against a kernel of known traffic."""
@@ -235,6 +274,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-laser", action="store_true", help="skip the two laser-on-foil boxes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU spatial decomposition "
@@ -249,6 +289,10 @@ def main() -> int:
     res32 = run_precision(w, "fp32", args.steps, args.warmup)
     res64 = None if args.no_fp64 else run_precision(w, "fp64", args.steps, args.warmup)
     adj = None if (args.no_adjoint or args.scale != 1) else adjoint_timing("fp32")
+    laser = None
+    if not args.no_laser and args.scale == 1:
+        from paper_1503_02464_amd.configs import laser_foil_2d, laser_foil_3d
+        laser = [laser_foil_timing(wl, args.steps, args.warmup) for wl in (laser_foil_2d(), laser_foil_3d())]
     if args.copy_probe:
         copy_probe()
     base = None if args.no_cpu_baseline else cpu_baseline(w)
@@ -278,6 +322,7 @@ def main() -> int:
                                                                   "phases_ms_per_launch",
                                                                   "yee_cell_updates_per_s")},
         "adjoint": adj,
+        "laser_foil": laser,
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -18,7 +18,8 @@
  * dB/dt = -curl E.
  *
  * Grid and staggering.  The box has n[0] x n[1] x n[2] cells (n[2] = 1 in 2D),
- * periodic in every dimension.  Every field component is an array of
+ * periodic in every dimension, except that the x faces may be open (open_x,
+ * below).  Every field component is an array of
  * n[0]*n[1]*n[2] values, x fastest (index i + n0*(j + n1*k)); the entry at
  * (i,j,k) sits at the component's Yee position:
  *   Ex (i+1/2, j, k)     Ey (i, j+1/2, k)     Ez (i, j, k+1/2)
@@ -98,7 +99,40 @@ typedef struct {
     int32_t sort_every;    /* pic_step re-sorts every this many steps (>= 1) */
     int64_t max_particles; /* the largest np of any species used with this context */
     int32_t current_accum; /* PIC_ACC_AUTO, PIC_ACC_FP32 (FP32 state only) or PIC_ACC_FP64 */
+    /* Open x faces (the paper gives no boundary details, Sec. 2; this is the
+     * absorbing boundary of laser-plasma boxes).  0: periodic in x.  1: the
+     * node planes i = 0 and i = n[0]-1 are the faces; E_y and E_z on them
+     * follow the first-order Mur condition (G. Mur, IEEE Trans. EMC 23 (1981)
+     * 377) and y, z stay periodic; a particle whose x cell leaves
+     * [absorb, n[0] - absorb) after a move deposits that move's current and
+     * is then removed: its weight becomes 0, the fused step skips it, and
+     * the next sort moves it behind every tile (tile_start[ntiles] is then the
+     * live count).  Weight-0 particles are always inert when open_x = 1. */
+    int32_t open_x;
+    int32_t absorb;        /* cells between each x face and the particle region, >= 2 shape_order + 2,
+                              and n[0] >= 2 absorb + 2 (open_x only) */
 } pic_params;
+
+/* A laser injected as a current sheet on the node plane x = plane dx (open
+ * x faces; the paper does not describe its laser source).  At time t the
+ * sheet adds to J_y (pol 1) or J_z (pol 2) on that plane
+ *   j0 exp(-r^2 / w0^2) exp(-2 ln2 (t - t0)^2 / tau^2) sin(omega (t - t0)),
+ * r the distance from the axis (y = yc, z = zc) at each J point, where j0 is
+ * chosen so that in the steady state the sheet radiates a plane wave of
+ * amplitude e0 to each side on the Yee lattice:
+ *   j0 = -e0 dt sin(k dx) / (dx^2 sin(omega dt / 2)),
+ *   sin(k dx / 2) = (dx / dt) sin(omega dt / 2),  dx = dx[0].
+ * w0 is the 1/e radius of the field, tau the FWHM of the intensity. */
+typedef struct {
+    int32_t plane;  /* 1 <= plane <= n[0] - 2 */
+    int32_t pol;    /* 1: E_y (J_y), 2: E_z (J_z, 3D only) */
+    double e0;      /* radiated amplitude, > 0 */
+    double omega;   /* angular frequency, below the lattice cut-off */
+    double w0;      /* > 0 */
+    double tau;     /* > 0 */
+    double t0;
+    double yc, zc;
+} pic_laser;
 
 /* The "em-field" element (Sec. 3.2): E, B and J as nine device arrays of
  * n[0]*n[1]*n[2] float or double values each (layout above). */
@@ -168,8 +202,16 @@ pic_status pic_deposit(pic_ctx *ctx, const pic_species *sp, pic_fields *f, void 
 pic_status pic_zero_current(pic_ctx *ctx, pic_fields *f, void *stream);
 
 /* Step 4 (Sec. 2, curl equations, Yee FDTD): B^{n+1/2} = B^n - dt/2 curl E^n,
- * E^{n+1} = E^n + dt (curl B^{n+1/2} - J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}. */
+ * E^{n+1} = E^n + dt (curl B^{n+1/2} - J^{n+1/2}), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}.
+ * With open_x, E_y and E_z on the two x faces take the Mur update instead. */
 pic_status pic_yee_step(pic_ctx *ctx, pic_fields *f, void *stream);
+
+/* Register the laser that pic_step adds to J at t = (step + 1/2) dt of every
+ * step (NULL: none; PIC_EINVAL without open_x or for bad parameters). */
+pic_status pic_set_laser(pic_ctx *ctx, const pic_laser *laser);
+/* Add the registered laser's sheet at time t to J (for callers composing a
+ * step from pic_gather_push / pic_deposit / pic_yee_step). */
+pic_status pic_laser_current(pic_ctx *ctx, pic_fields *f, double t, void *stream);
 
 /* Bin one species by tile (counting sort by tile index, x-fastest tile
  * numbering); order inside a tile is unspecified.  Writes tile_start, swaps
@@ -178,7 +220,9 @@ pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
 
 /* nsteps whole steps for nspecies species: sort when needed (unsorted species,
  * or every sort_every steps), clear J, fused gather + push + deposit per tile
- * with fields and current staged on chip, then the Yee update. */
+ * with fields and current staged on chip (and, with open_x, removal of the
+ * particles that left), the laser sheet if one is registered, then the Yee
+ * update. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields *f, int32_t nsteps, void *stream);
 
 /* FP64 diagnostics of the current state, accumulated in double on the device,
@@ -209,7 +253,10 @@ pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies
  * rollout must not re-sort between the two) and the fields E^n, B^n: reads
  * lam.J and lsp (dL/dx^{n+1}, dL/du^{n+1/2}), replaces lsp by dL/dx^n,
  * dL/du^{n-1/2}, and adds the transpose of the gather to lam.E and lam.B.
- * Call it after pic_yee_adjoint of the same step, once per species. */
+ * Call it after pic_yee_adjoint of the same step, once per species.
+ *
+ * The adjoint covers periodic boxes only: all three return PIC_EINVAL when
+ * open_x is set. */
 pic_status pic_energy_adjoint(pic_ctx *ctx, const pic_fields *f, pic_fields *lam, double scale, void *stream);
 pic_status pic_yee_adjoint(pic_ctx *ctx, pic_fields *lam, void *stream);
 pic_status pic_particle_adjoint(pic_ctx *ctx, const pic_species *state, const pic_fields *f, pic_fields *lam,

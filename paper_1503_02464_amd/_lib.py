@@ -36,6 +36,22 @@ class Params(ctypes.Structure):
         ("sort_every", ctypes.c_int32),
         ("max_particles", ctypes.c_int64),
         ("current_accum", ctypes.c_int32),
+        ("open_x", ctypes.c_int32),
+        ("absorb", ctypes.c_int32),
+    ]
+
+
+class Laser(ctypes.Structure):
+    _fields_ = [
+        ("plane", ctypes.c_int32),
+        ("pol", ctypes.c_int32),
+        ("e0", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("w0", ctypes.c_double),
+        ("tau", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("yc", ctypes.c_double),
+        ("zc", ctypes.c_double),
     ]
 
 
@@ -98,6 +114,8 @@ def load(path: str = LIB_PATH):
         "pic_deposit": (st, [ctx, P(Species), P(Fields), ctypes.c_void_p]),
         "pic_zero_current": (st, [ctx, P(Fields), ctypes.c_void_p]),
         "pic_yee_step": (st, [ctx, P(Fields), ctypes.c_void_p]),
+        "pic_set_laser": (st, [ctx, P(Laser)]),
+        "pic_laser_current": (st, [ctx, P(Fields), ctypes.c_double, ctypes.c_void_p]),
         "pic_sort": (st, [ctx, P(Species), ctypes.c_void_p]),
         "pic_step": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), ctypes.c_int32, ctypes.c_void_p]),
         "pic_diagnostics": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), P(ctypes.c_double), ctypes.c_void_p]),

@@ -9,6 +9,15 @@ the design notes):
   dx = 0.05 c/omega_p as in the small 2D box, dt = 0.7 of the limit.
 * macro weight w = n dV / ppc, so omega_p = 1 at n = 1 (paper eq. 2, the
   normalisation A absorbed into w; Sec. 3.3 per-particle weight).
+* laser boxes: lengths in c/omega_L (lambda = 2 pi, n_c = 1, a0 = peak E in
+  m_e c omega_L / e); open x faces with the particle region `absorb` cells in
+  from each face and the laser sheet on the node plane `laser_plane`; waist =
+  1/e field radius, duration = FWHM of the intensity, envelope centre
+  t0 = 1.5 tau; the beam waist sits on the sheet (its Rayleigh length, at
+  least 28 lambda, dwarfs the distance to the foil, so the foil sees the same
+  spot size within 2 %); foil front at 10 lambda (2D) and 5 lambda (3D);
+  ions (Z = 1, m = 1836 m_e) at the electrons' positions; the 3D box's
+  thermal spread 0.001 m_e c is a momentum spread for both species.
 """
 from __future__ import annotations
 
@@ -82,7 +91,98 @@ def diff_2d(n: int = 512) -> Workload:
                     seed=1004, tile=(16, 16, 1), extra={"checkpoint_every": 20, "src_sigma": 0.01})
 
 
-WORKLOADS = {"uniform-2d-64": uniform_2d_small, "thermal-3d-256": thermal_3d, "diff-2d-512": diff_2d}
+@dataclass
+class LaserFoil:
+    """A foil of electrons and ions hit by a laser injected near the low x face."""
+
+    name: str
+    dims: int
+    n: tuple
+    dx: tuple
+    cfl: float
+    order: int
+    steps: int
+    foil_x: tuple      # x cells [x0, x1) of the foil
+    density: float     # in n_c
+    ppc: int           # per species
+    u_sigma_e: float   # electron momentum spread (u = p / m_e c)
+    u_sigma_i: float   # ion momentum spread (u = p / m_i c)
+    a0: float
+    waist: float       # 1/e field radius
+    tau: float         # intensity FWHM
+    absorb: int = 8
+    laser_plane: int = 4
+    tile: tuple = (16, 16, 1)
+    seed: int = 1001
+    m_ion: float = 1836.0
+
+    @property
+    def dt(self) -> float:
+        return self.cfl * yee_dt_max(self.dims, self.dx)
+
+    @property
+    def ncells(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    @property
+    def cell_volume(self) -> float:
+        v = 1.0
+        for d in range(self.dims):
+            v *= self.dx[d]
+        return v
+
+    @property
+    def weight(self) -> float:
+        return self.density * self.cell_volume / self.ppc
+
+    @property
+    def t0(self) -> float:
+        return 1.5 * self.tau
+
+    def laser(self) -> dict:
+        yc = 0.5 * self.n[1] * self.dx[1]
+        zc = 0.5 * self.n[2] * self.dx[2] if self.dims == 3 else 0.0
+        return {"plane": self.laser_plane, "e0": self.a0, "omega": 1.0, "w0": self.waist, "tau": self.tau,
+                "t0": self.t0, "yc": yc, "zc": zc, "pol": 1}
+
+    def species(self):
+        """(electrons, ions) as numpy particle dicts, ions co-located."""
+        from . import inputs
+        e = inputs.foil(self.n, self.dims, self.foil_x[0], self.foil_x[1], self.ppc, self.u_sigma_e, self.weight,
+                        self.seed)
+        i = inputs.co_located(e, 1.0, self.m_ion, self.u_sigma_i, self.seed + 1)
+        return e, i
+
+
+def laser_foil_2d(scale: int = 1) -> LaserFoil:
+    """2D3V laser on a thin foil: 2048x1024 cells, dx = lambda/40, 0.98 CFL,
+    open x, periodic y; foil 0.5 lambda at 50 n_c, 64 ppc per species, cold;
+    a0 = 5, waist 4 lambda, 10 cycles; quadratic shape, 2000 steps.
+    ``scale`` divides the box, the foil position and thickness and the spot."""
+    lam = 2 * math.pi
+    dx = lam / 40
+    x0 = 400 // scale
+    return LaserFoil(f"laser-foil-2d3v-{2048 // scale}x{1024 // scale}-64ppc-quadratic", 2,
+                     (2048 // scale, 1024 // scale, 1), (dx, dx, 1.0), 0.98, 2, 2000, (x0, x0 + max(20 // scale, 2)),
+                     50.0, 64, 0.0, 0.0, 5.0, 4 * lam / scale, 10 * lam, tile=(16, 16, 1), seed=1001)
+
+
+def laser_foil_3d(scale: int = 1) -> LaserFoil:
+    """3D3V laser on a foil, one GPU's subdomain: 512x256x256 cells, dx =
+    lambda/20, 0.98 CFL, open x; foil 1 lambda at 30 n_c, 16 ppc per species,
+    momentum spread 0.001 m_e c; a0 = 10, waist 3 lambda, 10 cycles;
+    quadratic shape, FP32, 500 steps."""
+    lam = 2 * math.pi
+    dx = lam / 20
+    x0 = 100 // scale
+    return LaserFoil(f"laser-foil-3d3v-{512 // scale}x{256 // scale}x{256 // scale}-16ppc-quadratic", 3,
+                     (512 // scale, 256 // scale, 256 // scale), (dx, dx, dx), 0.98, 2, 500,
+                     (x0, x0 + max(20 // scale, 2)), 30.0, 16, 0.001, 0.001 / 1836.0, 10.0, 3 * lam / scale,
+                     10 * lam, tile=(8, 8, 8), seed=1003)
+
+
+WORKLOADS = {"uniform-2d-64": uniform_2d_small, "laser-foil-2d": laser_foil_2d, "thermal-3d-256": thermal_3d,
+             "laser-foil-3d": laser_foil_3d, "diff-2d-512": diff_2d}
 
 
 # Launch configuration of the fused step for the 3D benchmark workload, per

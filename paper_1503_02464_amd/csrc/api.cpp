@@ -101,6 +101,16 @@ void collect_timing(pic_ctx *c) {
   c->events.clear();
 }
 
+// B half step, E step (with the Mur faces when open_x), B half step.
+hipError_t yee_step(pic_ctx *c, const pic_fields &f, hipStream_t s) {
+  hipError_t e = pic::launch_yee_b(*c, f, 0.5, s);
+  if (e == hipSuccess && c->p.open_x) e = pic::launch_mur(*c, f, true, s);
+  if (e == hipSuccess) e = pic::launch_yee_e(*c, f, s);
+  if (e == hipSuccess && c->p.open_x) e = pic::launch_mur(*c, f, false, s);
+  if (e == hipSuccess) e = pic::launch_yee_b(*c, f, 0.5, s);
+  return e;
+}
+
 pic_status check_ws(pic_ctx *c) {
   if (!c->wsptr) return fail(c, PIC_ENOMEM, "no workspace set (pic_set_workspace)");
   return PIC_OK;
@@ -135,6 +145,9 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   if (p->current_accum != PIC_ACC_AUTO && p->current_accum != PIC_ACC_FP32 && p->current_accum != PIC_ACC_FP64)
     return PIC_EINVAL;
   if (p->precision == PIC_FP64 && p->current_accum == PIC_ACC_FP32) return PIC_EINVAL;
+  if (p->open_x != 0 && p->open_x != 1) return PIC_EINVAL;
+  if (p->open_x && (p->absorb < 2 * p->shape_order + 2 || p->n[0] < 2 * static_cast<int64_t>(p->absorb) + 2))
+    return PIC_EINVAL;
   for (int d = 0; d < 3; ++d) {
     const bool used = d < p->dims;
     if (used) {
@@ -215,20 +228,23 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.sort_rank = take(mp * 4);
   w.stray_count = take(4);
   w.stray_list = take(mp * 4);
-  const int64_t nbuckets = c->ntiles * c->levels;
-  if (pic::sort_scan_blocks(nbuckets) > pic::sort_scan_capacity()) {
+  // sort buckets: (tile, level) pairs plus one for particles removed at open faces
+  const int64_t nbuckets = c->ntiles * c->levels + 1;
+  if (pic::sort_scan_blocks(nbuckets) > pic::sort_scan_capacity() || nbuckets >= (int64_t(1) << 31) - 1) {
     delete c;
     return PIC_EINVAL;
   }
-  w.tile_count = take(static_cast<size_t>(nbuckets) * 4);
-  w.bucket_start = take((static_cast<size_t>(nbuckets) + 1) * 4);
+  w.stay_count = take(static_cast<size_t>(nbuckets) * 4);
+  w.arrive_count = take(static_cast<size_t>(nbuckets) * 4);
+  // bucket starts of the last sort, one slot per species (the next sort's hints)
+  w.bucket_start = take(static_cast<size_t>(pic::kMaxSpecies) * (nbuckets + 1) * 4);
   w.scan_partials = take(static_cast<size_t>(pic::sort_scan_blocks(nbuckets)) * 8);
-  w.node_count = take(static_cast<size_t>(ncells) * 4);
   w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
   w.result = take(16 * 8);
   w.rho = take(static_cast<size_t>(ncells) * 8);
   w.rho_prev = take(static_cast<size_t>(ncells) * 8);
   w.gauss_prev = take(static_cast<size_t>(ncells) * 8);
+  w.mur_old = take(p->open_x ? static_cast<size_t>(8) * p->n[1] * p->n[2] * c->elem : 0);
   w.total = off;
   *out = c;
   return PIC_OK;
@@ -309,11 +325,42 @@ pic_status pic_yee_step(pic_ctx *c, pic_fields *f, void *stream) {
   if (!c) return PIC_EINVAL;
   if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = pic::launch_yee_b(*c, *f, 0.5, s);
-  if (e == hipSuccess) e = pic::launch_yee_e(*c, *f, s);
-  if (e == hipSuccess) e = pic::launch_yee_b(*c, *f, 0.5, s);
+  hipError_t e = yee_step(c, *f, s);
   if (e != hipSuccess) return hip_fail(c, e, "yee_step");
   c->step += 1;
+  return PIC_OK;
+}
+
+pic_status pic_set_laser(pic_ctx *c, const pic_laser *L) {
+  if (!c) return PIC_EINVAL;
+  if (!L) {
+    c->has_laser = false;
+    return PIC_OK;
+  }
+  if (!c->p.open_x) return fail(c, PIC_EINVAL, "a laser needs open x faces");
+  if (L->plane < 1 || L->plane > c->p.n[0] - 2) return fail(c, PIC_EINVAL, "laser plane outside (0, n0-1)");
+  if (L->pol != 1 && !(L->pol == 2 && c->p.dims == 3)) return fail(c, PIC_EINVAL, "laser polarisation");
+  if (!(L->e0 > 0) || !(L->w0 > 0) || !(L->tau > 0) || !(L->omega > 0) || !std::isfinite(L->t0) ||
+      !std::isfinite(L->yc) || !std::isfinite(L->zc))
+    return fail(c, PIC_EINVAL, "laser parameters");
+  // lattice wavenumber of omega along x: sin(k dx/2) = (dx/dt) sin(omega dt/2)
+  const double dx = c->p.dx[0], dt = c->p.dt;
+  const double s = std::sin(0.5 * L->omega * dt);
+  const double arg = dx / dt * s;
+  if (!(arg < 1.0) || !(s > 0.0)) return fail(c, PIC_EINVAL, "laser frequency above the lattice cut-off");
+  const double k = 2.0 * std::asin(arg) / dx;
+  c->laser = *L;
+  c->laser_j0 = -L->e0 * dt * std::sin(k * dx) / (dx * dx * s);
+  c->has_laser = true;
+  return PIC_OK;
+}
+
+pic_status pic_laser_current(pic_ctx *c, pic_fields *f, double t, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  if (!c->has_laser) return fail(c, PIC_ESTATE, "no laser registered (pic_set_laser)");
+  hipError_t e = pic::launch_laser(*c, *f, t, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "laser_current");
   return PIC_OK;
 }
 
@@ -348,6 +395,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
     {
       PhaseTimer t(c, s, pic::kPhaseZero);
       for (int d = 0; d < 3 && e == hipSuccess; ++d) e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, s);
+      if (e == hipSuccess && c->has_laser) e = pic::launch_laser(*c, *f, (c->step + 0.5) * c->p.dt, s);
       if (e != hipSuccess) return hip_fail(c, e, "zero_current");
     }
     for (int i = 0; i < nspecies; ++i) {
@@ -358,9 +406,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
     }
     {
       PhaseTimer t(c, s, pic::kPhaseYee);
-      e = pic::launch_yee_b(*c, *f, 0.5, s);
-      if (e == hipSuccess) e = pic::launch_yee_e(*c, *f, s);
-      if (e == hipSuccess) e = pic::launch_yee_b(*c, *f, 0.5, s);
+      e = yee_step(c, *f, s);
       if (e != hipSuccess) return hip_fail(c, e, "yee");
     }
     c->step += 1;
@@ -398,6 +444,7 @@ pic_status pic_diagnostics(pic_ctx *c, const pic_species *sp, int32_t nspecies, 
 
 pic_status pic_energy_adjoint(pic_ctx *c, const pic_fields *f, pic_fields *lam, double scale, void *stream) {
   if (!c) return PIC_EINVAL;
+  if (c->p.open_x) return fail(c, PIC_EINVAL, "the adjoint covers periodic boxes only");
   if (!fields_ok(f) || !fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
   double dV = 1.0;
   for (int d = 0; d < c->p.dims; ++d) dV *= c->p.dx[d];
@@ -410,6 +457,7 @@ pic_status pic_energy_adjoint(pic_ctx *c, const pic_fields *f, pic_fields *lam, 
 
 pic_status pic_yee_adjoint(pic_ctx *c, pic_fields *lam, void *stream) {
   if (!c) return PIC_EINVAL;
+  if (c->p.open_x) return fail(c, PIC_EINVAL, "the adjoint covers periodic boxes only");
   if (!fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = pic::launch_yee_e(*c, *lam, s, -0.5, false);  // lamE -= dt/2 C_B lamB
@@ -423,6 +471,7 @@ pic_status pic_yee_adjoint(pic_ctx *c, pic_fields *lam, void *stream) {
 pic_status pic_particle_adjoint(pic_ctx *c, const pic_species *sp, const pic_fields *f, pic_fields *lam,
                                 pic_species_adjoint *lsp, void *stream) {
   if (!c) return PIC_EINVAL;
+  if (c->p.open_x) return fail(c, PIC_EINVAL, "the adjoint covers periodic boxes only");
   if (pic_status s = check_ws(c)) return s;
   if (!species_ok(c, sp, false)) return fail(c, PIC_EINVAL, "bad species");
   if (!fields_ok(f) || !fields_ok(lam)) return fail(c, PIC_EINVAL, "bad fields");
@@ -450,6 +499,9 @@ pic_status pic_check(pic_ctx *c, void *stream) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "check reset");
     if (flags & pic::kFlagCross) return fail(c, PIC_ECROSS, pic_status_string(PIC_ECROSS));
+    if (flags & pic::kFlagSort)
+      return fail(c, PIC_ESTATE, "sort: the species' tile_start runs did not match its particles "
+                                 "(edited without clearing sorted?)");
   }
   return PIC_OK;
 }

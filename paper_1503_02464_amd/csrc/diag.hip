@@ -122,12 +122,14 @@ __global__ void __launch_bounds__(kB) k_rho(const int32_t *cell, const T *o0, co
 // cell lies more than `slack` cells outside their tile add to HBM directly.
 template <typename T, int D, int M>
 __global__ void __launch_bounds__(256) k_rho_tiled(const int32_t *cell, const T *o0, const T *o1, const T *o2,
-                                                   const T *w, const int32_t *tile_start, double qdv, int b0,
-                                                   int b1, int m0, int m1, int m2, int n0, int n1, int n2, int L0,
-                                                   int L1, int L2, int nt0, int nt1, int slack, double *rho) {
+                                                   const T *w, const int32_t *tile_start, int64_t np, double qdv,
+                                                   int b0, int b1, int m0, int m1, int m2, int n0, int n1, int n2,
+                                                   int L0, int L1, int L2, int nt0, int nt1, int slack, double *rho) {
   extern __shared__ double box[];
   const int64_t tile = blockIdx.x;
-  const int64_t pbeg = tile_start[tile], pend = tile_start[tile + 1];
+  int64_t pbeg = tile_start[tile], pend = tile_start[tile + 1];
+  pbeg = pbeg < 0 ? 0 : (pbeg > np ? np : pbeg);
+  pend = pend > np ? np : pend;
   if (pbeg >= pend) return;
   const int T0[3] = {static_cast<int>(tile % nt0) * L0, static_cast<int>((tile / nt0) % nt1) * L1,
                      static_cast<int>(tile / ((int64_t)nt0 * nt1)) * L2};
@@ -281,8 +283,8 @@ hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_field
       if (box <= 64 * 1024) {
         hipLaunchKernelGGL((k_rho_tiled<T, D, M>), dim3(static_cast<unsigned>(c.ntiles)), dim3(kB), box, s, q.cell,
                            static_cast<const T *>(q.off[0]), static_cast<const T *>(q.off[1]),
-                           static_cast<const T *>(q.off[2]), static_cast<const T *>(q.w), q.tile_start, q.q / dV,
-                           c.bits[0], c.bits[1], (1 << c.bits[0]) - 1, (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1,
+                           static_cast<const T *>(q.off[2]), static_cast<const T *>(q.w), q.tile_start, q.np,
+                           q.q / dV, c.bits[0], c.bits[1], (1 << c.bits[0]) - 1, (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1,
                            static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), static_cast<int>(c.n[2]),
                            c.p.tile[0], c.p.tile[1], c.p.tile[2], c.ntile[0], c.ntile[1], sl, rho);
         continue;

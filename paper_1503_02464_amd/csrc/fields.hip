@@ -4,6 +4,8 @@
 // workgroups also read, so they are served mostly from L2.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -105,6 +107,58 @@ dim3 yee_grid(const pic_ctx &c, int block) {
 
 int yee_block(const pic_ctx &c) { return c.n[0] >= 256 ? 256 : static_cast<int>((c.n[0] + 63) / 64 * 64); }
 
+// Open x faces (first-order Mur on the tangential E of the face planes
+// i = 0 and i = n0-1).  k_mur_save keeps E_y, E_z^n of the planes
+// {0, 1, n0-2, n0-1} before the E update; k_mur_apply then replaces the
+// faces: E_face^{n+1} = E_next^n + a (E_next^{n+1} - E_face^n),
+// a = (dt - dx)/(dt + dx), "next" one plane inside.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mur_save(const T *__restrict__ Ey, const T *__restrict__ Ez, T *old, int n0,
+                                                  int64_t nyz) {
+  const int64_t jk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (jk >= nyz) return;
+  const int plane[4] = {0, 1, n0 - 2, n0 - 1};
+  const int64_t row = (int64_t)n0 * jk;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    old[q * nyz + jk] = Ey[row + plane[q]];
+    old[(4 + q) * nyz + jk] = Ez[row + plane[q]];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_mur_apply(T *Ey, T *Ez, const T *__restrict__ old, int n0, int64_t nyz,
+                                                   T a) {
+  const int64_t jk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (jk >= nyz) return;
+  const int64_t row = (int64_t)n0 * jk;
+  T *F[2] = {Ey, Ez};
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const T *o = old + 4 * c * nyz;
+    T *f = F[c] + row;
+    const T lo = o[nyz + jk] + a * (f[1] - o[jk]);
+    const T hi = o[2 * nyz + jk] + a * (f[n0 - 2] - o[3 * nyz + jk]);
+    f[0] = lo;
+    f[n0 - 1] = hi;
+  }
+}
+
+// Laser sheet: J[plane, j, k] += amp exp(-r^2 / w0^2), r from the axis at
+// the J component's staggered point; amp carries the time dependence.
+template <typename T>
+__global__ void __launch_bounds__(256) k_laser(T *J, int plane, int n0, int n1, int64_t nyz, int dims, double dy,
+                                               double dz, double sy, double sz, double amp, double inv_w02, double yc,
+                                               double zc) {
+  const int64_t jk = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (jk >= nyz) return;
+  const int j = static_cast<int>(jk % n1);
+  const int k = static_cast<int>(jk / n1);
+  const double y = (j + sy) * dy - yc;
+  const double z = dims == 3 ? (k + sz) * dz - zc : 0.0;
+  J[plane + (int64_t)n0 * jk] += static_cast<T>(amp * exp(-(y * y + z * z) * inv_w02));
+}
+
 }  // namespace
 
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s) {
@@ -159,6 +213,51 @@ hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s) {
                        static_cast<float *>(ptr), n);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_mur(const pic_ctx &c, const pic_fields &f, bool save, hipStream_t s) {
+  const int64_t nyz = c.n[1] * c.n[2];
+  const unsigned blocks = static_cast<unsigned>((nyz + 255) / 256);
+  const int n0 = static_cast<int>(c.n[0]);
+  const double a = (c.p.dt - c.p.dx[0]) / (c.p.dt + c.p.dx[0]);
+  if (c.p.precision == PIC_FP64) {
+    auto *old = c.wsp<double>(c.ws.mur_old);
+    if (save)
+      hipLaunchKernelGGL(k_mur_save<double>, dim3(blocks), dim3(256), 0, s, static_cast<const double *>(f.E[1]),
+                         static_cast<const double *>(f.E[2]), old, n0, nyz);
+    else
+      hipLaunchKernelGGL(k_mur_apply<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(f.E[1]),
+                         static_cast<double *>(f.E[2]), old, n0, nyz, a);
+  } else {
+    auto *old = c.wsp<float>(c.ws.mur_old);
+    if (save)
+      hipLaunchKernelGGL(k_mur_save<float>, dim3(blocks), dim3(256), 0, s, static_cast<const float *>(f.E[1]),
+                         static_cast<const float *>(f.E[2]), old, n0, nyz);
+    else
+      hipLaunchKernelGGL(k_mur_apply<float>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(f.E[1]),
+                         static_cast<float *>(f.E[2]), old, n0, nyz, static_cast<float>(a));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_laser(const pic_ctx &c, const pic_fields &f, double t, hipStream_t s) {
+  const pic_laser &L = c.laser;
+  const double env = std::exp(-2.0 * std::log(2.0) * (t - L.t0) * (t - L.t0) / (L.tau * L.tau));
+  const double amp = c.laser_j0 * env * std::sin(L.omega * (t - L.t0));
+  const int64_t nyz = c.n[1] * c.n[2];
+  const unsigned blocks = static_cast<unsigned>((nyz + 255) / 256);
+  const double sy = L.pol == 1 ? 0.5 : 0.0, sz = L.pol == 2 ? 0.5 : 0.0;
+  const double dz = c.p.dims == 3 ? c.p.dx[2] : 0.0;
+  void *J = f.J[L.pol];
+  if (c.p.precision == PIC_FP64)
+    hipLaunchKernelGGL(k_laser<double>, dim3(blocks), dim3(256), 0, s, static_cast<double *>(J), L.plane,
+                       static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), nyz, c.p.dims, c.p.dx[1], dz, sy, sz, amp,
+                       1.0 / (L.w0 * L.w0), L.yc, L.zc);
+  else
+    hipLaunchKernelGGL(k_laser<float>, dim3(blocks), dim3(256), 0, s, static_cast<float *>(J), L.plane,
+                       static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), nyz, c.p.dims, c.p.dx[1], dz, sy, sz, amp,
+                       1.0 / (L.w0 * L.w0), L.yc, L.zc);
   return hipGetLastError();
 }
 

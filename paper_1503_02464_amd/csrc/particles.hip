@@ -16,7 +16,9 @@ struct SpeciesArgs {
   int32_t *cell;
   T *off[3];
   T *u[3];
-  const T *w;
+  T *w;         // written only to remove a particle at an open x face
+  int open;     // 1: open x faces; weight-0 particles are inert
+  int xlo, xhi; // live x cells [xlo, xhi) when open
   T h;          // q dt / (2 m)
   T dtdx[3];    // dt / dx_d
   T jc[3];      // (q / dV)(dx_d / dt), times w per particle
@@ -51,6 +53,13 @@ __device__ __forceinline__ int32_t pack(const int c[3], const GridArgs &g) {
                               (static_cast<uint32_t>(c[2]) << (g.bits[0] + g.bits[1])));
 }
 
+// After a move: remove the particle (weight 0) if its x cell left the live
+// range of an open box.  Its current for this move is already deposited.
+template <typename T>
+__device__ __forceinline__ void absorb_if_out(const SpeciesArgs<T> &s, int64_t p, int cx) {
+  if (s.open && (cx < s.xlo || cx >= s.xhi)) s.w[p] = T(0);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_particle(const SpeciesArgs<T> &s, int64_t p, T o[3], T u[3]) {
 #pragma unroll
@@ -69,6 +78,10 @@ __global__ void __launch_bounds__(256) k_gather_push(SpeciesArgs<T> s, GridArgs 
                                                      int32_t *flags) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= s.np) return;
+  if (s.open && s.w[p] == T(0)) {  // removed: inert, and the deposit skips it
+    save_cell[p] = -1;
+    return;
+  }
   int c[3];
   const int32_t packed = s.cell[p];
   unpack(packed, g, c);
@@ -128,6 +141,7 @@ __global__ void __launch_bounds__(256) k_deposit(SpeciesArgs<T> s, GridArgs g, G
   T jz = T(0);
   if (D == 2) jz = w * s.jz * u[2] * ig;
   deposit<T, D, M>(J, c0, o0, dc, o1, jc, jz);
+  absorb_if_out(s, p, c1[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,7 +248,10 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     const int64_t per = gridDim.x / 8;
     tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
   }
-  const int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
+  // clamp to the species: ranges that a failed sort left beyond np are ignored
+  int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
+  pbeg = pbeg < 0 ? 0 : (pbeg > s.np ? s.np : pbeg);
+  pend = pend > s.np ? s.np : pend;
   if (pbeg >= pend) return;
   const int tx = static_cast<int>(tile % t.ntile[0]);
   const int ty = static_cast<int>((tile / t.ntile[0]) % t.ntile[1]);
@@ -297,6 +314,8 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
     }
     if (!inside) continue;
+    const T w = s.w[p];
+    if (s.open && w == T(0)) continue;  // removed at an open face, until the next sort drops it
     T o[3], u[3];
     load_particle<T, D>(s, p, o, u);
     T eb[6];
@@ -307,7 +326,6 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     int dc[3] = {0, 0, 0};
     const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
     if (!ok) atomicOr(&flags[0], kFlagCross);
-    const T w = s.w[p];
     const T jz = D == 2 ? s.jz * u[2] * ig : T(0);
     const bool wide = ok && crosses<T, D, M>(o, dc, on);
     if (ok && !wide) {
@@ -351,6 +369,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     s.u[0][p] = u[0];
     s.u[1][p] = u[1];
     s.u[2][p] = u[2];
+    absorb_if_out(s, p, c[0]);
   }
   __syncthreads();
 
@@ -399,6 +418,8 @@ __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g
   const int64_t n = *count;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = list[k];
+    const T w = s.w[p];
+    if (s.open && w == T(0)) continue;  // removed at an open face
     int c[3];
     unpack(s.cell[p], g, c);
     T o[3], u[3];
@@ -411,7 +432,6 @@ __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g
     int dc[3] = {0, 0, 0};
     const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
     if (!ok) atomicOr(&flags[0], kFlagCross);
-    const T w = s.w[p];
     const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
     const T jz = D == 2 ? w * s.jz * u[2] * ig : T(0);
     if (ok) deposit<T, D, M>(gj, c, o, dc, on, jc, jz);
@@ -424,6 +444,7 @@ __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g
     s.u[0][p] = u[0];
     s.u[1][p] = u[1];
     s.u[2][p] = u[2];
+    absorb_if_out(s, p, c[0]);
   }
 }
 
@@ -439,7 +460,10 @@ SpeciesArgs<T> species_args(const pic_ctx &c, const pic_species &sp) {
     s.off[d] = static_cast<T *>(sp.off[d]);
     s.u[d] = static_cast<T *>(sp.u[d]);
   }
-  s.w = static_cast<const T *>(sp.w);
+  s.w = static_cast<T *>(sp.w);
+  s.open = c.p.open_x;
+  s.xlo = c.p.open_x ? c.p.absorb : 0;
+  s.xhi = c.p.open_x ? static_cast<int>(c.n[0]) - c.p.absorb : static_cast<int>(c.n[0]);
   const double dt = c.p.dt;
   double dV = 1.0;
   for (int d = 0; d < c.p.dims; ++d) dV *= c.p.dx[d];

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pic.h"
@@ -35,19 +36,20 @@ struct Workspace {
   size_t sort_rank = 0;   // int32[max_particles]
   size_t stray_count = 0; // int32: particles the tiled kernel left outside their LDS box
   size_t stray_list = 0;  // int32[max_particles]: their indices
-  size_t tile_count = 0;  // int32[ntiles * levels]: particles per (tile, level) bucket
-  size_t bucket_start = 0;   // int32[ntiles * levels + 1]
+  size_t stay_count = 0;    // int32[ntiles * levels]: per (tile, level) bucket, particles that stayed in the tile
+  size_t arrive_count = 0;  // int32[ntiles * levels]: per bucket, the others
+  size_t bucket_start = 0;   // int32[kMaxSpecies][nbuckets + 1]: bucket starts of each species' last sort
   size_t scan_partials = 0;  // int64[scan blocks]
-  size_t node_count = 0;     // int32[ncells]: particles per nearest node (level ranks)
   size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
   size_t result = 0;      // double[16]
   size_t rho = 0;         // double[ncells]
   size_t rho_prev = 0;    // double[ncells]
   size_t gauss_prev = 0;  // double[ncells]
+  size_t mur_old = 0;     // T[8][n1 * n2]: E_y, E_z^n of the planes next to the open x faces
   size_t total = 0;
 };
 
-enum Flag : int32_t { kFlagCross = 1 };
+enum Flag : int32_t { kFlagCross = 1, kFlagSort = 2 };
 
 enum Phase { kPhaseSort = 0, kPhaseZero = 1, kPhasePush = 2, kPhaseYee = 3 };
 
@@ -69,6 +71,13 @@ struct pic_ctx {
   bool acc64 = true;  // LDS current box accumulated in double
   int32_t cross_cap = 0;  // capacity of the fused kernel's wide-window list
   int32_t levels = 16;  // rank levels per tile in the sort (particles sharing a node go to distinct levels)
+  // (tile_start array, particle count) of every species this context sorted
+  // (at most kMaxSpecies; entry i owns bucket-start slot i of the workspace):
+  // the next sort of that species ranks by the runs tile_start describes
+  std::vector<std::pair<const int32_t *, int64_t>> sorted_runs;
+  bool has_laser = false;
+  pic_laser laser{};
+  double laser_j0 = 0.0;  // sheet amplitude radiating laser.e0 on the lattice
   pic::Workspace ws;
   char *wsptr = nullptr;
   size_t wsbytes = 0;
@@ -101,6 +110,11 @@ hipError_t launch_gather_push(const pic_ctx &c, const pic_species &sp, const pic
 hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 hipError_t launch_push_deposit_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
+// Open x faces: save = true keeps E_y, E_z^n next to the faces (before the E
+// update), save = false applies the Mur update to the faces (after it).
+hipError_t launch_mur(const pic_ctx &c, const pic_fields &f, bool save, hipStream_t s);
+// J += the registered laser sheet at time t.
+hipError_t launch_laser(const pic_ctx &c, const pic_fields &f, double t, hipStream_t s);
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s);
 // E += frac dt curl B (- dt J when with_j)
 hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s, double frac = 1.0, bool with_j = true);
@@ -109,7 +123,7 @@ hipError_t launch_scale_copy(const pic_ctx &c, void *const dst[3], const void *c
                              hipStream_t s);
 hipError_t launch_particle_adjoint(const pic_ctx &c, const pic_species &sp, const pic_fields &f,
                                    const pic_fields &lam, const pic_species_adjoint &lsp, hipStream_t s);
-hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s);
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s);
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,

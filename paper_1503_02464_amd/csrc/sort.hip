@@ -6,10 +6,14 @@
 // kernel deposit into disjoint LDS windows and its atomics never collide on
 // one address (on gfx950 such collisions serialise the LDS).
 //
-// Passes: (1) node ranks from per-node counters; bucket (tile, level) slots
-// from per-bucket counters, one atomic per distinct bucket per wavefront;
-// (2) exclusive scan of the bucket counters (multi-block), which also yields
-// the tile starts; (3) every particle copied to its slot in the second set.
+// Passes: (1) one workgroup per run of particles that the previous sort put in
+// one tile (or per fixed chunk when the species is not sorted) ranks each
+// particle among those of the run that share its node, with counters in LDS;
+// bucket (tile, level) slots come from per-bucket counters in HBM, one atomic
+// per distinct bucket per wavefront; (2) exclusive scan of the bucket counters
+// (multi-block), which also yields the tile starts; (3) every particle copied
+// to its slot in the second set.  Particles of one node that sat in different
+// runs can share a level; that only costs the fused kernel an LDS conflict.
 #include <hip/hip_runtime.h>
 
 #include "pic_internal.h"
@@ -55,35 +59,138 @@ __device__ __forceinline__ int wave_slot(bool active, int key, int32_t *counts) 
   return slot;
 }
 
+// LDS rank counters of the count pass: nodes hash to kRankSlots counters by
+// the low bits of their coordinates, enough bits per dimension to keep every
+// node a run can reach apart (a collision only merges two nodes' levels).
+constexpr int kRankBits = 12;
+constexpr int kRankSlots = 1 << kRankBits;
+constexpr int kCountBlock = 1024;
+constexpr int64_t kCountChunk = 4096;  // particles per workgroup when not sorted
+// LDS words of the per-level bitmaps over a tile's nodes (and of their prefix
+// counts) that order the particles staying in their tile by node.
+constexpr int kOrderWords = 2048;
+constexpr int kLevelShift = 20;  // stayer rank word: level << 20 | local node
+
+struct RankGeom {
+  int hbits[3], hmask[3];  // node hash
+  int nl[3];               // nodes per dimension a tile's particles can be nearest to
+  int words;               // bitmap words per level; 0 disables the node order
+};
+
+// Pass 1.  Workgroup b ranks the particles of run b (those the previous sort
+// put in tile b), or of chunk b when the species is not sorted.  A particle's
+// level is its rank among the run's particles of its node.  A particle still
+// in tile b (a "stayer") is ranked inside its (tile, level) bucket by its
+// node, from a bitmap of the nodes the run's stayers occupy at that level, so
+// the bucket holds the stayers in node order; every other particle (an
+// "arrival" in its bucket) takes a slot after the bucket's stayers from an
+// HBM counter, and its key is stored as -bucket-1.
 template <typename T, int M>
-__global__ void __launch_bounds__(256) k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2,
-                                                    int64_t np, SortGeom g, int levels, int32_t *node_count,
-                                                    int32_t *key, int32_t *rank, int32_t *bucket_count) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = p < np;
-  int bucket = -1;
-  if (active) {
-    int c[3];
-    unpack_cell(cell[p], g, c);
-    const int tile = c[0] / g.L[0] + g.ntile0 * (c[1] / g.L[1] + g.ntile1 * (c[2] / g.L[2]));
-    // nearest node (quadratic shape) or cell (linear shape), periodic
-    int nd[3] = {c[0], c[1], c[2]};
-    if (M == 2) {
-      const T o[3] = {o0[p], o1[p], g.dims == 3 ? o2[p] : T(0)};
+__global__ void __launch_bounds__(kCountBlock)
+    k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w, int open, int64_t np,
+                 SortGeom g, RankGeom rg, int levels, const int32_t *runs, const int32_t *hints, int64_t nruns,
+                 int32_t *key, int32_t *rank, int32_t *stay_count, int32_t *arrive_count) {
+  __shared__ int32_t counter[kRankSlots];
+  __shared__ uint32_t bits[kOrderWords];
+  __shared__ int32_t prefix[kOrderWords];
+  const int64_t b = blockIdx.x;
+  const bool order = runs != nullptr && b < nruns && rg.words > 0;
+  const int nwords = order ? levels * rg.words : 0;
+  for (int i = threadIdx.x; i < kRankSlots; i += kCountBlock) counter[i] = 0;
+  for (int i = threadIdx.x; i < nwords; i += kCountBlock) bits[i] = 0u;
+  __syncthreads();
+  int64_t lo, hi;
+  if (runs) {  // run b of the previous sort; the extra last workgroup takes any tail
+    lo = b < nruns ? runs[b] : runs[nruns];
+    hi = b < nruns ? runs[b + 1] : np;
+  } else {
+    lo = b * kCountChunk;
+    hi = lo + kCountChunk;
+  }
+  lo = lo < 0 ? 0 : (lo > np ? np : lo);
+  hi = hi < lo ? lo : (hi > np ? np : hi);
+  int T0[3] = {0, 0, 0};
+  if (order) {
+    T0[0] = static_cast<int>(b % g.ntile0) * g.L[0];
+    T0[1] = static_cast<int>((b / g.ntile0) % g.ntile1) * g.L[1];
+    T0[2] = static_cast<int>(b / ((int64_t)g.ntile0 * g.ntile1)) * g.L[2];
+  }
+  // The run is walked level segment by level segment of the previous sort
+  // (hints: its bucket starts), with a barrier after every pass, so a node's
+  // particles meet the LDS counter in their previous level order and keep
+  // their levels; the permutation then stays close to the identity.  The
+  // segments are clamped to partition [lo, hi) whatever the hints hold.
+  const int32_t *hint = (hints && runs && b < nruns) ? hints + b * levels : nullptr;
+  const int nseg = hint ? levels : 1;
+  const int64_t dead = (int64_t)g.ntile0 * g.ntile1 * (g.n[2] / g.L[2]) * levels;  // bucket of removed particles
+  int64_t seg_hi = lo;
+  for (int sgi = 0; sgi < nseg; ++sgi) {
+    const int64_t seg_lo = seg_hi;
+    if (sgi == nseg - 1) {
+      seg_hi = hi;
+    } else {
+      int64_t h = hint[sgi + 1];
+      seg_hi = h < seg_lo ? seg_lo : (h > hi ? hi : h);
+    }
+  for (int64_t base = seg_lo; base < seg_hi; base += kCountBlock) {  // uniform trip count per workgroup
+    const int64_t p = base + threadIdx.x;
+    const bool active = p < seg_hi;
+    int bucket = -1;
+    bool stay = false;
+    int word = 0;
+    if (active && open && w[p] == T(0)) {  // removed at an open face: to the end, out of every tile
+      bucket = static_cast<int>(dead);
+    } else if (active) {
+      int c[3];
+      unpack_cell(cell[p], g, c);
+      const int tile = c[0] / g.L[0] + g.ntile0 * (c[1] / g.L[1] + g.ntile1 * (c[2] / g.L[2]));
+      // nearest node (quadratic shape) or cell (linear shape), unwrapped
+      int nd[3] = {c[0], c[1], c[2]};
+      if (M == 2) {
+        const T o[3] = {o0[p], o1[p], g.dims == 3 ? o2[p] : T(0)};
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d < g.dims && o[d] >= T(0.5)) nd[d] = (nd[d] + 1 == g.n[d]) ? 0 : nd[d] + 1;
+        for (int d = 0; d < 3; ++d)
+          if (d < g.dims && o[d] >= T(0.5)) nd[d] += 1;
+      }
+      const int slot = (nd[0] & rg.hmask[0]) | ((nd[1] & rg.hmask[1]) << rg.hbits[0]) |
+                       ((nd[2] & rg.hmask[2]) << (rg.hbits[0] + rg.hbits[1]));
+      int level = atomicAdd(&counter[slot], 1);
+      level = level < levels - 1 ? level : levels - 1;
+      bucket = tile * levels + level;
+      stay = order && tile == b && level < levels - 1;
+      if (stay) {  // a stayer's nearest node lies in [T0, T0 + L] per dimension
+        const int v = (nd[0] - T0[0]) + rg.nl[0] * ((nd[1] - T0[1]) + rg.nl[1] * (nd[2] - T0[2]));
+        atomicOr(&bits[level * rg.words + (v >> 5)], 1u << (v & 31));
+        word = (level << kLevelShift) | v;
       }
     }
-    const int64_t node = nd[0] + (int64_t)g.n[0] * (nd[1] + (int64_t)g.n[1] * nd[2]);
-    int level = atomicAdd(&node_count[node], 1);
-    level = level < levels - 1 ? level : levels - 1;
-    bucket = tile * levels + level;
+    const int slot = wave_slot(active && !stay, bucket, arrive_count);
+    if (active) {
+      key[p] = stay ? bucket : -bucket - 1;
+      rank[p] = stay ? word : slot;
+    }
+    __syncthreads();
   }
-  const int slot = wave_slot(active, bucket, bucket_count);
-  if (active) {
-    key[p] = bucket;
-    rank[p] = slot;
+  }
+  if (!order) return;
+  __syncthreads();
+  for (int l = threadIdx.x; l < levels; l += kCountBlock) {  // per level: prefix popcounts, stayer count
+    int run = 0;
+    for (int w = 0; w < rg.words; ++w) {
+      prefix[l * rg.words + w] = run;
+      run += __popc(bits[l * rg.words + w]);
+    }
+    stay_count[b * levels + l] = run;
+  }
+  __syncthreads();
+  for (int64_t base = lo; base < hi; base += kCountBlock) {  // the same thread revisits its own particles
+    const int64_t p = base + threadIdx.x;
+    if (p < hi && key[p] >= 0) {
+      const int r = rank[p];
+      const int v = r & ((1 << kLevelShift) - 1);
+      const int wi = (r >> kLevelShift) * rg.words + (v >> 5);
+      rank[p] = prefix[wi] + __popc(bits[wi] & ((1u << (v & 31)) - 1u));
+    }
   }
 }
 
@@ -109,13 +216,14 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *sh, 
   return incl - v;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_partials(const int32_t *counts, int64_t n, int64_t *partials) {
+__global__ void __launch_bounds__(kScanBlock) k_scan_partials(const int32_t *ca, const int32_t *cb, int64_t n,
+                                                              int64_t *partials) {
   __shared__ int64_t sh[kScanBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i)
-    if (base + i < n) s += counts[base + i];
+    if (base + i < n) s += (int64_t)ca[base + i] + cb[base + i];
   int64_t total;
   block_exclusive_scan(s, sh, total);
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
@@ -141,16 +249,16 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_partials_top(int64_t *parti
   }
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *counts, int64_t n, const int64_t *partials,
-                                                          int levels, int32_t *start, int32_t *tile_start,
-                                                          int64_t ntiles) {
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *ca, const int32_t *cb, int64_t n,
+                                                          const int64_t *partials, int levels, int32_t *start,
+                                                          int32_t *tile_start, int64_t ntiles) {
   __shared__ int64_t sh[kScanBlock];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int64_t v[kScanItems];
   int64_t s = 0;
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < n ? counts[base + i] : 0;
+    v[i] = base + i < n ? (int64_t)ca[base + i] + cb[base + i] : 0;
     s += v[i];
   }
   int64_t total;
@@ -160,25 +268,37 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *counts
     const int64_t idx = base + i;
     if (idx < n) {
       start[idx] = static_cast<int32_t>(run);
-      if (idx % levels == 0) tile_start[idx / levels] = static_cast<int32_t>(run);
+      // entry ntiles * levels is the bucket of removed particles: its start
+      // closes the last tile
+      if (idx % levels == 0 && idx / levels <= ntiles) tile_start[idx / levels] = static_cast<int32_t>(run);
     }
     run += v[i];
   }
-  if (base <= n - 1 && n - 1 < base + kScanItems) {  // the thread holding the last entry writes the totals
+  if (base <= n - 1 && n - 1 < base + kScanItems)  // the thread holding the last entry writes the total
     start[n] = static_cast<int32_t>(run);
-    tile_start[ntiles] = static_cast<int32_t>(run);
-  }
 }
 
+// Pass 3.  A stayer goes to start[bucket] + its node rank, an arrival after
+// the bucket's stayers.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_sort_scatter(int64_t np, const int32_t *key, const int32_t *rank,
-                                                      const int32_t *start, const int32_t *cell, const T *o0,
+                                                      const int32_t *start, const int32_t *stay,
+                                                      const int32_t *cell, const T *o0,
                                                       const T *o1, const T *o2, const T *u0, const T *u1,
                                                       const T *u2, const T *w, int32_t *cell_d, T *o0d, T *o1d,
-                                                      T *o2d, T *u0d, T *u1d, T *u2d, T *wd) {
+                                                      T *o2d, T *u0d, T *u1d, T *u2d, T *wd, int64_t nbuckets,
+                                                      int32_t *flags) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= np) return;
-  const int64_t q = start[key[p]] + rank[p];
+  const int32_t k = key[p];
+  const int64_t bk = k >= 0 ? k : -(int64_t)k - 1;
+  int64_t q = -1;
+  if (bk < nbuckets) q = (int64_t)start[bk] + rank[p] + (k >= 0 ? 0 : stay[bk]);
+  if (q < 0 || q >= np || (bk < nbuckets && q >= start[bk + 1])) {
+    // the runs handed to the count pass did not partition the particles
+    atomicOr(&flags[0], kFlagSort);
+    return;
+  }
   cell_d[q] = cell[p];
   o0d[q] = o0[p];
   o1d[q] = o1[p];
@@ -189,36 +309,71 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int64_t np, const int32_t 
   wd[q] = w[p];
 }
 
+RankGeom rank_geom(const pic_ctx &c) {
+  // a run's nodes span at most tile + 2 slack + 1 per dimension
+  RankGeom h{};
+  int total = 0;
+  for (int d = 0; d < 3; ++d) {
+    int span = d < c.p.dims ? c.p.tile[d] + 2 * c.p.slack + 1 : 1;
+    int b = 0;
+    while ((1 << b) < span) ++b;
+    h.hbits[d] = b;
+    total += b;
+  }
+  while (total > kRankBits) {  // trim the widest dimension; collisions only cost conflicts
+    int dmax = 0;
+    for (int d = 1; d < 3; ++d)
+      if (h.hbits[d] > h.hbits[dmax]) dmax = d;
+    --h.hbits[dmax];
+    --total;
+  }
+  int64_t vol = 1;
+  for (int d = 0; d < 3; ++d) {
+    h.hmask[d] = (1 << h.hbits[d]) - 1;
+    h.nl[d] = d < c.p.dims ? c.p.tile[d] + (c.p.shape_order == 2 ? 1 : 0) : 1;
+    vol *= h.nl[d];
+  }
+  const int64_t words = (vol + 31) / 32;
+  h.words = (words * c.levels <= kOrderWords && vol < (1 << kLevelShift)) ? static_cast<int>(words) : 0;
+  return h;
+}
+
 template <typename T>
-void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
+void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_runs, const int32_t *hints,
+           hipStream_t s) {
   const auto *o0 = static_cast<const T *>(sp.off[0]);
   const auto *o1 = static_cast<const T *>(sp.off[1]);
   const auto *o2 = static_cast<const T *>(c.p.dims == 3 ? sp.off[2] : sp.off[0]);
-  int32_t *nodes = c.wsp<int32_t>(c.ws.node_count);
   int32_t *keys = c.wsp<int32_t>(c.ws.sort_key);
   int32_t *ranks = c.wsp<int32_t>(c.ws.sort_rank);
-  int32_t *buckets = c.wsp<int32_t>(c.ws.tile_count);
+  int32_t *stay = c.wsp<int32_t>(c.ws.stay_count);
+  int32_t *arrive = c.wsp<int32_t>(c.ws.arrive_count);
+  const int32_t *runs = by_runs ? sp.tile_start : nullptr;
+  const int64_t nruns = by_runs ? c.ntiles : 0;
+  const unsigned blocks = static_cast<unsigned>(by_runs ? c.ntiles + 1 : (sp.np + kCountChunk - 1) / kCountChunk);
+  const RankGeom rg = rank_geom(c);
+  const auto *w = static_cast<const T *>(sp.w);
+  const int open = c.p.open_x;
   if (c.p.shape_order == 2)
-    hipLaunchKernelGGL((k_sort_count<T, 2>), dim3(blocks), dim3(256), 0, s, sp.cell, o0, o1, o2, sp.np, g,
-                       c.levels, nodes, keys, ranks, buckets);
+    hipLaunchKernelGGL((k_sort_count<T, 2>), dim3(blocks), dim3(kCountBlock), 0, s, sp.cell, o0, o1, o2, w, open,
+                       sp.np, g, rg, c.levels, runs, hints, nruns, keys, ranks, stay, arrive);
   else
-    hipLaunchKernelGGL((k_sort_count<T, 1>), dim3(blocks), dim3(256), 0, s, sp.cell, o0, o1, o2, sp.np, g,
-                       c.levels, nodes, keys, ranks, buckets);
+    hipLaunchKernelGGL((k_sort_count<T, 1>), dim3(blocks), dim3(kCountBlock), 0, s, sp.cell, o0, o1, o2, w, open,
+                       sp.np, g, rg, c.levels, runs, hints, nruns, keys, ranks, stay, arrive);
 }
 
 template <typename T, int D>
-void scatter(const pic_ctx &c, const pic_species &sp, hipStream_t s) {
+void scatter(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
   hipLaunchKernelGGL((k_sort_scatter<T, D>), dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
-                     c.wsp<int32_t>(c.ws.sort_rank), c.wsp<int32_t>(c.ws.bucket_start), sp.cell,
+                     c.wsp<int32_t>(c.ws.sort_rank), start, c.wsp<int32_t>(c.ws.stay_count), sp.cell,
                      static_cast<const T *>(sp.off[0]), static_cast<const T *>(sp.off[1]),
                      static_cast<const T *>(sp.off[2]), static_cast<const T *>(sp.u[0]),
                      static_cast<const T *>(sp.u[1]), static_cast<const T *>(sp.u[2]),
                      static_cast<const T *>(sp.w), sp.cell_alt, static_cast<T *>(sp.off_alt[0]),
                      static_cast<T *>(sp.off_alt[1]), static_cast<T *>(sp.off_alt[2]),
                      static_cast<T *>(sp.u_alt[0]), static_cast<T *>(sp.u_alt[1]), static_cast<T *>(sp.u_alt[2]),
-                     static_cast<T *>(sp.w_alt));
+                     static_cast<T *>(sp.w_alt), c.ntiles * c.levels + 1, c.wsp<int32_t>(c.ws.flags));
 }
 
 }  // namespace
@@ -226,12 +381,35 @@ void scatter(const pic_ctx &c, const pic_species &sp, hipStream_t s) {
 int64_t sort_scan_blocks(int64_t nbuckets) { return (nbuckets + kScanTile - 1) / kScanTile; }
 int64_t sort_scan_capacity() { return static_cast<int64_t>(kScanBlock) * kScanItems; }
 
-hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s) {
-  const int64_t nb = c.ntiles * c.levels;
-  int32_t *buckets = c.wsp<int32_t>(c.ws.tile_count);
-  hipError_t e = launch_fill_zero(buckets, nb, 4, s);
-  if (e == hipSuccess) e = launch_fill_zero(c.wsp<int32_t>(c.ws.node_count), c.ncells, 4, s);
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
+  // buckets: (tile, level) for every tile, then one for removed particles
+  const int64_t nb = c.ntiles * c.levels + 1;
+  int32_t *stay = c.wsp<int32_t>(c.ws.stay_count);
+  int32_t *arrive = c.wsp<int32_t>(c.ws.arrive_count);
+  hipError_t e = launch_fill_zero(stay, nb, 4, s);
+  if (e == hipSuccess) e = launch_fill_zero(arrive, nb, 4, s);
   if (e != hipSuccess) return e;
+  // The previous sort's tile runs (and its bucket starts, kept in the
+  // species' slot) stay valid while the particle set is the one this context
+  // sorted last into this tile_start array.
+  int slot = -1;
+  bool by_runs = false;
+  for (size_t i = 0; i < c.sorted_runs.size(); ++i)
+    if (c.sorted_runs[i].first == sp.tile_start) {
+      slot = static_cast<int>(i);
+      by_runs = c.sorted_runs[i].second == sp.np && sp.sorted;
+    }
+  if (slot < 0) {
+    if (c.sorted_runs.size() < static_cast<size_t>(kMaxSpecies)) {
+      slot = static_cast<int>(c.sorted_runs.size());
+      c.sorted_runs.emplace_back(sp.tile_start, -1);
+    } else {  // more species than slots: share the last one, without hints
+      slot = kMaxSpecies - 1;
+      by_runs = false;
+      c.sorted_runs[slot].first = sp.tile_start;
+    }
+  }
+  int32_t *start = c.wsp<int32_t>(c.ws.bucket_start) + static_cast<size_t>(slot) * (nb + 1);
   if (sp.np > 0) {
     SortGeom g{};
     g.bits0 = c.bits[0];
@@ -246,24 +424,25 @@ hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s) {
     g.ntile0 = c.ntile[0];
     g.ntile1 = c.ntile[1];
     g.dims = c.p.dims;
+    const int32_t *hints = by_runs ? start : nullptr;
     if (c.p.precision == PIC_FP64)
-      count<double>(c, sp, g, s);
+      count<double>(c, sp, g, by_runs, hints, s);
     else
-      count<float>(c, sp, g, s);
+      count<float>(c, sp, g, by_runs, hints, s);
   }
   const int64_t nblk = sort_scan_blocks(nb);
   int64_t *partials = c.wsp<int64_t>(c.ws.scan_partials);
-  hipLaunchKernelGGL(k_scan_partials, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, buckets, nb,
+  hipLaunchKernelGGL(k_scan_partials, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, stay, arrive, nb,
                      partials);
   hipLaunchKernelGGL(k_scan_partials_top, dim3(1), dim3(kScanBlock), 0, s, partials, nblk);
-  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, buckets, nb, partials,
-                     c.levels, c.wsp<int32_t>(c.ws.bucket_start), sp.tile_start, c.ntiles);
+  hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, stay, arrive, nb,
+                     partials, c.levels, start, sp.tile_start, c.ntiles);
   if (sp.np > 0) {
     const bool f64 = c.p.precision == PIC_FP64;
     if (f64)
-      (c.p.dims == 3) ? scatter<double, 3>(c, sp, s) : scatter<double, 2>(c, sp, s);
+      (c.p.dims == 3) ? scatter<double, 3>(c, sp, start, s) : scatter<double, 2>(c, sp, start, s);
     else
-      (c.p.dims == 3) ? scatter<float, 3>(c, sp, s) : scatter<float, 2>(c, sp, s);
+      (c.p.dims == 3) ? scatter<float, 3>(c, sp, start, s) : scatter<float, 2>(c, sp, start, s);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -275,6 +454,7 @@ hipError_t launch_sort(const pic_ctx &c, pic_species &sp, hipStream_t s) {
   }
   std::swap(sp.w, sp.w_alt);
   sp.sorted = 1;
+  c.sorted_runs[slot].second = sp.np;
   return hipSuccess;
 }
 

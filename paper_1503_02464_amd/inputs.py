@@ -41,6 +41,37 @@ def uniform_plasma(n: tuple, dims: int, ppc: int, u_sigma: float, weight: float,
     return {"q": float(q), "m": float(m), "cell": cell, "off": off, "u": np.ascontiguousarray(u), "w": w}
 
 
+def foil(n: tuple, dims: int, x0: int, x1: int, ppc: int, u_sigma: float, weight: float, seed: int,
+         q: float = -1.0, m: float = 1.0) -> dict:
+    """A slab: ``ppc`` particles in every cell with x cell in [x0, x1) over the
+    whole y (and z) extent, ordered cell by cell, offsets uniform, momenta
+    Gaussian (sigma 0: cold)."""
+    g = rng(seed)
+    nx = x1 - x0
+    ncell = int(nx * n[1] * n[2])
+    npart = ncell * ppc
+    lin = np.repeat(np.arange(ncell, dtype=np.int64), ppc)
+    cell = np.zeros((3, npart), np.int32)
+    cell[0] = x0 + lin % nx
+    cell[1] = (lin // nx) % n[1]
+    cell[2] = lin // (nx * n[1])
+    off = np.zeros((3, npart), np.float64)
+    off[:dims] = g.random((dims, npart))
+    u = g.normal(0.0, u_sigma, (3, npart)) if u_sigma > 0 else np.zeros((3, npart))
+    w = np.full(npart, weight, np.float64)
+    return {"q": float(q), "m": float(m), "cell": cell, "off": off, "u": np.ascontiguousarray(u), "w": w}
+
+
+def co_located(sp: dict, q: float, m: float, u_sigma: float, seed: int) -> dict:
+    """A second species at exactly the positions of ``sp`` (so the initial
+    charge density of the pair vanishes), with its own Gaussian momenta."""
+    g = rng(seed)
+    npart = sp["w"].shape[0]
+    u = g.normal(0.0, u_sigma, (3, npart)) if u_sigma > 0 else np.zeros((3, npart))
+    return {"q": float(q), "m": float(m), "cell": sp["cell"].copy(), "off": sp["off"].copy(),
+            "u": np.ascontiguousarray(u), "w": sp["w"].copy()}
+
+
 def shuffle(sp: dict, seed: int) -> dict:
     """Random permutation of the particles (order carries no physics)."""
     perm = rng(seed).permutation(sp["w"].shape[0])

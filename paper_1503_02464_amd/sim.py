@@ -68,11 +68,13 @@ class Simulation:
     dims 2 or 3; n cells per dim (n[2] = 1 in 2D); dx spacings; dt step;
     order 1 (linear) or 2 (quadratic); precision "fp32" or "fp64"; tile cells
     per sort tile; slack guard cells; sort_every steps between sorts;
-    current_accum the LDS current accumulation type ("auto" = fp64)."""
+    current_accum the LDS current accumulation type ("auto" = fp64); open_x
+    opens the x faces (Mur fields, particles removed outside
+    [absorb, n0 - absorb) cells)."""
 
     def __init__(self, dims: int, n: tuple, dx: tuple, dt: float, order: int, precision: str = "fp32",
                  tile: tuple = (8, 8, 8), slack: int = 1, sort_every: int = 4, max_particles: int = 0,
-                 current_accum: str = "auto", device: str = "cuda"):
+                 current_accum: str = "auto", open_x: bool = False, absorb: int = 0, device: str = "cuda"):
         self.lib = L.load()
         self.dims = dims
         self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
@@ -97,6 +99,10 @@ class Simulation:
         p.sort_every = sort_every
         p.max_particles = int(max_particles)
         p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64}[current_accum]
+        p.open_x = 1 if open_x else 0
+        p.absorb = int(absorb)
+        self.open_x = bool(open_x)
+        self.absorb = int(absorb)
         self.params = p
         ctx = ctypes.c_void_p()
         st = self.lib.pic_init(ctypes.byref(p), ctypes.byref(ctx))
@@ -231,6 +237,22 @@ class Simulation:
     def yee_step(self) -> None:
         self._call(self.lib.pic_yee_step(self.ctx, ctypes.byref(self.fstruct), ctypes.c_void_p(_stream())),
                    "pic_yee_step")
+
+    def set_laser(self, plane: int, e0: float, omega: float = 1.0, w0: float = 1e30, tau: float = 1e30,
+                  t0: float = 0.0, yc: float = 0.0, zc: float = 0.0, pol: int = 1) -> None:
+        """Register the laser current sheet that every step adds (open x only)."""
+        las = L.Laser(plane=int(plane), pol=int(pol), e0=float(e0), omega=float(omega), w0=float(w0), tau=float(tau),
+                      t0=float(t0), yc=float(yc), zc=float(zc))
+        self._call(self.lib.pic_set_laser(self.ctx, ctypes.byref(las)), "pic_set_laser")
+
+    def laser_current(self, t: float) -> None:
+        """J += the registered laser sheet at time t."""
+        self._call(self.lib.pic_laser_current(self.ctx, ctypes.byref(self.fstruct), float(t),
+                                              ctypes.c_void_p(_stream())), "pic_laser_current")
+
+    def live(self, s: SpeciesState) -> torch.Tensor:
+        """Mask of the particles not removed at an open face (weight != 0)."""
+        return s.current()["w"][:s.np] != 0
 
     def sort(self, s: SpeciesState) -> None:
         self._call(self.lib.pic_sort(self.ctx, ctypes.byref(s.struct), ctypes.c_void_p(_stream())), "pic_sort")

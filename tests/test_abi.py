@@ -17,7 +17,7 @@ def lib():
 
 
 def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec=L.PIC_FP32, tile=(8, 8, 8),
-           slack=1, sort_every=4, maxp=1000, acc=L.PIC_ACC_AUTO):
+           slack=1, sort_every=4, maxp=1000, acc=L.PIC_ACC_AUTO, open_x=0, absorb=0):
     p = L.Params()
     p.dims = dims
     p.n = L._c3i(*n)
@@ -30,6 +30,8 @@ def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec
     p.sort_every = sort_every
     p.max_particles = maxp
     p.current_accum = acc
+    p.open_x = open_x
+    p.absorb = absorb
     return p
 
 
@@ -80,6 +82,8 @@ def test_cfl_limit(lib, cfl, want):
     dict(n=(64, 64, 64), tile=(32, 8, 8)),  # local cells must fit the packed 6-bit range
     dict(prec=L.PIC_FP64, tile=(16, 16, 16), n=(32, 32, 32)),  # LDS tile beyond 160 KB
     dict(acc=3), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32),
+    dict(open_x=2), dict(open_x=1, absorb=5),  # absorb below 2 * order + 2
+    dict(open_x=1, absorb=8),  # n[0] < 2 * absorb + 2
 ])
 def test_invalid_params(lib, kw):
     st, ctx = init(lib, params(**kw))
@@ -106,8 +110,8 @@ def test_header_and_binding_agree():
 
 
 def test_struct_layout_matches_header(tmp_path):
-    """Offsets of every field of the three structs, from gcc on pic.h, equal the ctypes mirror."""
-    structs = {"pic_params": L.Params, "pic_fields": L.Fields, "pic_species": L.Species}
+    """Offsets of every field of the ABI structs, from gcc on pic.h, equal the ctypes mirror."""
+    structs = {"pic_params": L.Params, "pic_fields": L.Fields, "pic_species": L.Species, "pic_laser": L.Laser}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -138,3 +142,34 @@ def test_cell_packing_roundtrip():
         packed = sim.pack_cells(cell, bits)
         assert packed.dtype == np.int32
         assert np.array_equal(sim.unpack_cells(packed, bits), cell)
+
+
+def laser(**kw):
+    las = L.Laser(plane=3, pol=1, e0=1.0, omega=2.0, w0=0.3, tau=1.0, t0=0.5, yc=0.4, zc=0.4)
+    for k, v in kw.items():
+        setattr(las, k, v)
+    return las
+
+
+def test_laser_validation(lib):
+    st, ctx = init(lib, params(open_x=1, absorb=6))
+    assert st == L.PIC_OK
+    assert lib.pic_set_laser(ctx, ctypes.byref(laser())) == L.PIC_OK
+    assert lib.pic_set_laser(ctx, None) == L.PIC_OK  # none
+    for kw in (dict(plane=0), dict(plane=15), dict(pol=3), dict(e0=0.0), dict(w0=-1.0), dict(tau=0.0),
+               dict(omega=1e4), dict(t0=float("nan"))):
+        assert lib.pic_set_laser(ctx, ctypes.byref(laser(**kw))) == L.PIC_EINVAL, kw
+    f = L.Fields()
+    assert lib.pic_laser_current(ctx, ctypes.byref(f), 0.0, None) == L.PIC_EINVAL  # null field pointers
+    lib.pic_destroy(ctx)
+    st, ctx = init(lib, params())  # periodic: no laser, no adjoint restrictions
+    assert lib.pic_set_laser(ctx, ctypes.byref(laser())) == L.PIC_EINVAL
+    lib.pic_destroy(ctx)
+
+
+def test_adjoint_refuses_open_faces(lib):
+    st, ctx = init(lib, params(open_x=1, absorb=6))
+    f = L.Fields()
+    assert lib.pic_yee_adjoint(ctx, ctypes.byref(f), None) == L.PIC_EINVAL
+    assert lib.pic_energy_adjoint(ctx, ctypes.byref(f), ctypes.byref(f), 1.0, None) == L.PIC_EINVAL
+    lib.pic_destroy(ctx)

@@ -1,0 +1,150 @@
+"""The two laser-on-foil boxes (open x faces, laser sheet, electrons and
+ions, quadratic shape) on the GPU against the FP64 oracle.
+
+Full size, in the launch configuration of their workloads (FP32 state,
+16x16 tiles in 2D, 8x8x8 in 3D, slack 1, sort every 4 steps): two steps from
+the seeded foil with small seeded fields added everywhere (so that the cold
+foil moves at once); the oracle checks sampled particles of the second step
+(no re-sort in between, so indices match) and E, B everywhere from the GPU's
+current.  A scaled 2D box runs many FP64 steps with the foil next to the
+laser plane and must match the oracle to 1e-12."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_helpers import TOL, compare_fields, compare_species, grid, unique_weights
+from paper_1503_02464_amd import inputs
+from paper_1503_02464_amd.configs import laser_foil_2d, laser_foil_3d
+from paper_1503_02464_amd.sim import Simulation, unpack_cells
+
+pytestmark = pytest.mark.gpu
+
+
+def ora_grid(w):
+    return O.Grid(w.dims, w.n, w.dx, w.dt, w.order)
+
+
+def make(w, prec, max_particles, sort_every=4):
+    return Simulation(w.dims, w.n, w.dx, w.dt, w.order, prec, tile=w.tile, slack=1, sort_every=sort_every,
+                      max_particles=max_particles, open_x=True, absorb=w.absorb)
+
+
+def ora_laser(w):
+    return O.Laser(**w.laser())
+
+
+@pytest.fixture(scope="module", params=["2d", "3d"])
+def full(request):
+    w = laser_foil_2d() if request.param == "2d" else laser_foil_3d()
+    e, i = w.species()
+    f = inputs.round_fields_f32(inputs.random_fields(w.ncells, 0.05, seed=w.seed + 7))
+    s = make(w, "fp32", e["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    s.set_laser(**w.laser())
+    hs = [s.add_species(e), s.add_species(i)]
+    q0 = s.diagnostics()["Q"]
+    s.step(1)  # sorts both species, pushes, deposits, laser, Yee
+    f1 = s.get_fields()
+    st1 = []
+    for h in hs:
+        cur = h.current()
+        st1.append({"cell": cur["cell"][:h.np].clone(), "off": [t[:h.np].clone() for t in cur["off"]],
+                    "u": [t[:h.np].clone() for t in cur["u"]], "w": cur["w"][:h.np].clone()})
+    s.step(1)
+    s.check()
+    f2 = s.get_fields()
+    d2 = s.diagnostics()
+    yield dict(w=w, s=s, hs=hs, st1=st1, f1=f1, f2=f2, q0=q0, d2=d2, sizes=(e["w"].shape[0], i["w"].shape[0]))
+    s.close()
+
+
+def host(sim, st, idx, q, m):
+    """Particles idx of a device state as an oracle species."""
+    i = torch.as_tensor(idx, device="cuda")
+    return {"q": q, "m": m, "cell": unpack_cells(st["cell"][i].cpu().numpy(), sim.bits),
+            "off": np.stack([t[i].double().cpu().numpy() for t in st["off"]]),
+            "u": np.stack([t[i].double().cpu().numpy() for t in st["u"]]),
+            "w": st["w"][i].double().cpu().numpy()}
+
+
+def test_sampled_particles_full_size(full):
+    w, s = full["w"], full["s"]
+    g = ora_grid(w)
+    t = TOL["fp32"]
+    for k, (h, q, m) in enumerate(zip(full["hs"], (-1.0, 1.0), (1.0, w.m_ion))):
+        idx = np.sort(inputs.rng(500 + k).choice(h.np, 4096, replace=False))
+        before = host(s, full["st1"][k], idx, q, m)
+        cur = h.current()
+        after = host(s, {"cell": cur["cell"], "off": cur["off"], "u": cur["u"], "w": cur["w"]}, idx, q, m)
+        ref = O.copy_species(before)
+        EB = O.gather(g, full["f1"]["E"], full["f1"]["B"], ref["cell"], ref["off"])
+        ref["u"] = O.boris(q, m, g.dt, EB, ref["u"])
+        ref["cell"], ref["off"], _, bad = O.move(g, ref["u"], ref["cell"], ref["off"])
+        assert bad == 0
+        O.absorb(ref, w.absorb, w.n[0] - w.absorb)
+        assert np.array_equal(after["w"], ref["w"])
+        du = np.max(np.abs(after["u"] - ref["u"])) / max(np.max(np.abs(ref["u"])), 1e-30)
+        n = np.array(g.n)[:, None]
+        dx = (after["cell"] + after["off"] - ref["cell"] - ref["off"] + n / 2) % n - n / 2
+        assert du <= t["u"], (k, du)
+        assert np.max(np.abs(dx)) <= t["pos"], (k, np.max(np.abs(dx)))
+
+
+def test_fields_everywhere_full_size(full):
+    """E^2, B^2 from E^1, B^1 and the GPU's J^{3/2} (particles + laser sheet)
+    through the oracle's open-face Yee update."""
+    g = ora_grid(full["w"])
+    f = {k: v.copy() for k, v in full["f1"].items()}
+    f["J"] = full["f2"]["J"].copy()
+    O.yee_step_open(g, f)
+    for k in ("E", "B"):
+        err = np.max(np.abs(full["f2"][k] - f[k])) / np.max(np.abs(f[k]))
+        assert err <= TOL["fp32"][k], (k, err)
+
+
+def test_charge_and_count_full_size(full):
+    """Nothing reaches the faces in two steps: no particle removed, weights
+    untouched, and the FP64 total charge of the neutral pair unchanged up to
+    the summation order."""
+    scale = 0.0
+    for h, n in zip(full["hs"], full["sizes"]):
+        assert h.np == n
+        assert int(full["s"].live(h).sum().item()) == n
+        scale += float(h.current()["w"][:n].double().abs().sum().item())
+    assert abs(full["d2"]["Q"] - full["q0"]) <= 1e-12 * scale
+    assert np.isfinite(full["d2"]["UE"]) and np.isfinite(full["d2"]["UB"]) and full["d2"]["UE"] > 0
+
+
+def test_scaled_2d_foil_at_the_laser_fp64():
+    """The 2D box scaled by 8 (256x128), the foil moved next to the laser
+    sheet and the pulse shortened so that it drives the foil within the run:
+    30 fused FP64 steps, electrons and ions, against the oracle."""
+    w = laser_foil_2d(8)
+    w.foil_x = (14, 16)
+    w.tau = 3.0
+    w.laser_plane = 6
+    w.ppc = 8
+    w.u_sigma_e = 0.05
+    w.a0 = 1.0
+    e, i = w.species()
+    e = unique_weights(e, 510, scale=w.weight)
+    i = unique_weights(i, 511, scale=w.weight)
+    g = ora_grid(w)
+    s = make(w, "fp64", e["w"].shape[0])
+    s.set_laser(**w.laser())
+    he, hi = s.add_species(e), s.add_species(i)
+    ref_f = O.new_fields(g)
+    ref = [O.copy_species(e), O.copy_species(i)]
+    las = ora_laser(w)
+    for n in range(30):
+        s.step(1)
+        ref, bad, _ = O.step_open(g, ref_f, ref, w.absorb, w.n[0] - w.absorb, las, n)
+        assert bad == 0
+    s.check()
+    live = lambda sp: {k: (v[..., sp["w"] != 0] if isinstance(v, np.ndarray) else v) for k, v in sp.items()}
+    compare_species(g, "fp64", live(s.get_species(he)), ref[0], "electrons")
+    compare_species(g, "fp64", live(s.get_species(hi)), ref[1], "ions")
+    compare_fields("fp64", s.get_fields(), ref_f, what="scaled laser foil")
+    assert np.max(np.abs(ref_f["E"][1])) > 0.5 * w.a0  # the pulse is there
+    s.close()

@@ -125,6 +125,58 @@ def test_sort(prec, dims, order):
     s.close()
 
 
+@pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
+def test_sort_by_previous_runs(prec, dims, order):
+    """A re-sort of a species this context sorted before ranks particles run
+    by run (the tile ranges of the previous sort): after pushing it must still
+    be the tile permutation the oracle's sort gives for the moved particles."""
+    g = small_grid(dims, order)
+    sp, f = clustered(g, prec, seed=61)
+    tile = tiles(dims)
+    s = make_sim(g, prec, tile, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(3)  # the first step sorts (unsorted input), the next two only push
+    before = s.get_species(h)
+    s.sort(h)
+    out = s.get_species(h)
+    start = s.tile_start(h)
+    keys = O.tile_keys(g, tile, out["cell"])
+    assert np.all(np.diff(keys) >= 0), "keys not sorted"
+    ref, ref_start = O.tile_sort(g, tile, before)
+    assert np.array_equal(start, ref_start), "tile offsets differ"
+    a, b = by_weight(out), by_weight(ref)
+    assert np.array_equal(a["w"], b["w"])
+    for k in ("cell", "off", "u"):
+        assert np.array_equal(a[k], b[k]), k
+    s.check()
+    s.close()
+
+
+def test_sort_rejects_runs_that_do_not_partition():
+    """If the tile ranges a sorted species carries were overwritten so that they
+    cover particles twice, the re-sort writes nothing out of bounds and the
+    next check reports PIC_ESTATE."""
+    import torch
+    from paper_1503_02464_amd._lib import PicError
+    g = small_grid(3, 2)
+    sp, _ = clustered(g, "fp32", seed=62)
+    tile = tiles(3)
+    s = make_sim(g, "fp32", tile, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    h = s.add_species(sp)
+    s.sort(h)
+    npart = h.np
+    bad = torch.zeros_like(h.tile_start)
+    bad[1::2] = npart  # runs [0, np), [np, 0) -> empty, [0, np), ...: every particle counted several times
+    bad[-1] = npart
+    h.tile_start.copy_(bad)
+    s.sort(h)
+    with pytest.raises(PicError) as e:
+        s.check()
+    assert e.value.status == -7  # PIC_ESTATE
+    s.close()
+
+
 def test_c1_100_steps_fp64():
     """The small 2D workload (64x64, 4 ppc, linear, 0.7 CFL) for 100 steps, FP64."""
     from paper_1503_02464_amd.configs import uniform_2d_small
