@@ -5,7 +5,7 @@ per cell (134,217,728 particles), Maxwellian momenta with spread 0.05 m_e c,
 quadratic shape, dx = 0.05 c/omega_p, dt = 0.7 of the Yee limit; synthetic,
 seeded inputs resident in HBM before timing starts.
 
-One step = the whole forward step: the tile sort (every 4th step, amortised),
+One step = the whole forward step: the tile sort (every 8th step, amortised),
 clearing J, the fused gather + Boris + Esirkepov deposit per tile, and the Yee
 update.  value = particle pushes per second over the timed steps.
 

@@ -1,20 +1,21 @@
 // Counting sort of a species by tile, with the particles of each tile laid
-// out level by level: a particle's level is its rank among the particles
-// sharing its nearest grid node (its cell, for the linear shape), and the
-// particles of one tile are ordered by (level, arrival).  Within a level no
-// two particles share a node, so the 64 lanes of a wavefront of the fused
-// kernel deposit into disjoint LDS windows and its atomics never collide on
-// one address (on gfx950 such collisions serialise the LDS).
+// out level by level: particles sharing a nearest grid node (a cell, for the
+// linear shape) get distinct levels, and a tile's particles are ordered by
+// level, then by node.  The 64 lanes of a wavefront of the fused kernel then
+// hold particles of distinct nodes, so their LDS atomics never collide on one
+// address (on gfx950 such collisions serialise the LDS), and neighbouring
+// lanes hold neighbouring nodes, so their LDS reads spread over the banks.
 //
 // Passes: (1) one workgroup per run of particles that the previous sort put in
-// one tile (or per fixed chunk when the species is not sorted) ranks each
-// particle among those of the run that share its node, with counters in LDS;
-// bucket (tile, level) slots come from per-bucket counters in HBM, one atomic
-// per distinct bucket per wavefront; (2) exclusive scan of the bucket counters
-// (multi-block), which also yields the tile starts; (3) every particle copied
-// to its slot in the second set.  Particles of one node that sat in different
-// runs can share a level; that only costs the fused kernel an LDS conflict.
+// one tile (or per fixed chunk when the species is not sorted yet) assigns
+// levels and ranks with LDS counters and bitmaps (see k_sort_count); (2) an
+// exclusive scan of the bucket counts (multi-block) gives the bucket starts
+// and the tile starts; (3) every particle is copied to its slot in the
+// second set.  Particles removed at an open face go to one last bucket behind
+// every tile.
 #include <hip/hip_runtime.h>
+
+#include <cstdint>
 
 #include "pic_internal.h"
 
@@ -78,13 +79,22 @@ struct RankGeom {
 };
 
 // Pass 1.  Workgroup b ranks the particles of run b (those the previous sort
-// put in tile b), or of chunk b when the species is not sorted.  A particle's
-// level is its rank among the run's particles of its node.  A particle still
-// in tile b (a "stayer") is ranked inside its (tile, level) bucket by its
-// node, from a bitmap of the nodes the run's stayers occupy at that level, so
-// the bucket holds the stayers in node order; every other particle (an
-// "arrival" in its bucket) takes a slot after the bucket's stayers from an
-// HBM counter, and its key is stored as -bucket-1.
+// put in tile b), or of chunk b when the species is not sorted yet.
+//  * Chunk: a particle's level is its rank among the chunk's particles of its
+//    node (LDS counters); every particle takes a slot in its bucket from an
+//    HBM counter (an "arrival": its key is stored as -bucket-1).
+//  * Run: a particle still in tile b (a "stayer") keeps the level it had
+//    (the segment of the previous sort's buckets it sits in) unless another
+//    stayer of its node claimed that level first; then it takes the node's
+//    lowest free level.  Claims are bits of per-level bitmaps over the tile's
+//    nodes.  Stayers are then ranked inside their (tile, level) bucket by node,
+//    so a bucket holds its stayers in node order and a particle whose node and
+//    level did not change keeps its place: the permutation stays close to a
+//    shift, and the scatter's writes stay coalesced.  A particle that left
+//    the tile keeps its level and arrives after the stayers of its new bucket.
+constexpr int kMaxLevels = 64;
+constexpr int32_t kDeferred = INT32_MIN;  // a stayer whose previous level was taken
+
 template <typename T, int M>
 __global__ void __launch_bounds__(kCountBlock)
     k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w, int open, int64_t np,
@@ -93,12 +103,9 @@ __global__ void __launch_bounds__(kCountBlock)
   __shared__ int32_t counter[kRankSlots];
   __shared__ uint32_t bits[kOrderWords];
   __shared__ int32_t prefix[kOrderWords];
+  __shared__ int64_t seg[kMaxLevels + 1];
   const int64_t b = blockIdx.x;
-  const bool order = runs != nullptr && b < nruns && rg.words > 0;
-  const int nwords = order ? levels * rg.words : 0;
-  for (int i = threadIdx.x; i < kRankSlots; i += kCountBlock) counter[i] = 0;
-  for (int i = threadIdx.x; i < nwords; i += kCountBlock) bits[i] = 0u;
-  __syncthreads();
+  const bool order = runs != nullptr && hints != nullptr && b < nruns && rg.words > 0;
   int64_t lo, hi;
   if (runs) {  // run b of the previous sort; the extra last workgroup takes any tail
     lo = b < nruns ? runs[b] : runs[nruns];
@@ -109,34 +116,32 @@ __global__ void __launch_bounds__(kCountBlock)
   }
   lo = lo < 0 ? 0 : (lo > np ? np : lo);
   hi = hi < lo ? lo : (hi > np ? np : hi);
+  if (order) {
+    for (int i = threadIdx.x; i < levels * rg.words; i += kCountBlock) bits[i] = 0u;
+    if (threadIdx.x == 0) {  // previous level segments, clamped to partition [lo, hi)
+      seg[0] = lo;
+      for (int l = 1; l < levels; ++l) {
+        const int64_t h = hints[b * levels + l];
+        seg[l] = h < seg[l - 1] ? seg[l - 1] : (h > hi ? hi : h);
+      }
+      seg[levels] = hi;
+    }
+  } else {
+    for (int i = threadIdx.x; i < kRankSlots; i += kCountBlock) counter[i] = 0;
+  }
+  __syncthreads();
   int T0[3] = {0, 0, 0};
   if (order) {
     T0[0] = static_cast<int>(b % g.ntile0) * g.L[0];
     T0[1] = static_cast<int>((b / g.ntile0) % g.ntile1) * g.L[1];
     T0[2] = static_cast<int>(b / ((int64_t)g.ntile0 * g.ntile1)) * g.L[2];
   }
-  // The run is walked level segment by level segment of the previous sort
-  // (hints: its bucket starts), with a barrier after every pass, so a node's
-  // particles meet the LDS counter in their previous level order and keep
-  // their levels; the permutation then stays close to the identity.  The
-  // segments are clamped to partition [lo, hi) whatever the hints hold.
-  const int32_t *hint = (hints && runs && b < nruns) ? hints + b * levels : nullptr;
-  const int nseg = hint ? levels : 1;
   const int64_t dead = (int64_t)g.ntile0 * g.ntile1 * (g.n[2] / g.L[2]) * levels;  // bucket of removed particles
-  int64_t seg_hi = lo;
-  for (int sgi = 0; sgi < nseg; ++sgi) {
-    const int64_t seg_lo = seg_hi;
-    if (sgi == nseg - 1) {
-      seg_hi = hi;
-    } else {
-      int64_t h = hint[sgi + 1];
-      seg_hi = h < seg_lo ? seg_lo : (h > hi ? hi : h);
-    }
-  for (int64_t base = seg_lo; base < seg_hi; base += kCountBlock) {  // uniform trip count per workgroup
+  for (int64_t base = lo; base < hi; base += kCountBlock) {  // uniform trip count per workgroup
     const int64_t p = base + threadIdx.x;
-    const bool active = p < seg_hi;
+    const bool active = p < hi;
     int bucket = -1;
-    bool stay = false;
+    int kind = 0;  // 0 arrival, 1 stayer with its level, 2 stayer deferred
     int word = 0;
     if (active && open && w[p] == T(0)) {  // removed at an open face: to the end, out of every tile
       bucket = static_cast<int>(dead);
@@ -152,38 +157,73 @@ __global__ void __launch_bounds__(kCountBlock)
         for (int d = 0; d < 3; ++d)
           if (d < g.dims && o[d] >= T(0.5)) nd[d] += 1;
       }
-      const int slot = (nd[0] & rg.hmask[0]) | ((nd[1] & rg.hmask[1]) << rg.hbits[0]) |
+      int level;
+      if (order) {
+        int l0 = 0;  // previous level: the last segment starting at or before p
+        for (int l = 1; l < levels; ++l) l0 = seg[l] <= p ? l : l0;
+        level = l0;
+        if (tile == b) {  // a stayer's nearest node lies in [T0, T0 + L] per dimension
+          const int v = (nd[0] - T0[0]) + rg.nl[0] * ((nd[1] - T0[1]) + rg.nl[1] * (nd[2] - T0[2]));
+          const uint32_t m = 1u << (v & 31);
+          if (l0 < levels - 1 && !(atomicOr(&bits[l0 * rg.words + (v >> 5)], m) & m)) {
+            kind = 1;
+            word = (l0 << kLevelShift) | v;
+          } else {
+            kind = 2;
+            word = v;
+          }
+        }
+      } else {
+        const int hs = (nd[0] & rg.hmask[0]) | ((nd[1] & rg.hmask[1]) << rg.hbits[0]) |
                        ((nd[2] & rg.hmask[2]) << (rg.hbits[0] + rg.hbits[1]));
-      int level = atomicAdd(&counter[slot], 1);
-      level = level < levels - 1 ? level : levels - 1;
-      bucket = tile * levels + level;
-      stay = order && tile == b && level < levels - 1;
-      if (stay) {  // a stayer's nearest node lies in [T0, T0 + L] per dimension
-        const int v = (nd[0] - T0[0]) + rg.nl[0] * ((nd[1] - T0[1]) + rg.nl[1] * (nd[2] - T0[2]));
-        atomicOr(&bits[level * rg.words + (v >> 5)], 1u << (v & 31));
-        word = (level << kLevelShift) | v;
+        level = atomicAdd(&counter[hs], 1);
+        level = level < levels - 1 ? level : levels - 1;
       }
+      bucket = tile * levels + level;
     }
-    const int slot = wave_slot(active && !stay, bucket, arrive_count);
+    const int slot = wave_slot(active && kind == 0, bucket, arrive_count);
     if (active) {
-      key[p] = stay ? bucket : -bucket - 1;
-      rank[p] = stay ? word : slot;
+      key[p] = kind == 1 ? bucket : (kind == 2 ? kDeferred : -bucket - 1);
+      rank[p] = kind == 0 ? slot : word;
     }
-    __syncthreads();
-  }
   }
   if (!order) return;
   __syncthreads();
+  // deferred stayers take their node's lowest free level (or overflow into the
+  // last level as arrivals)
+  for (int64_t base = lo; base < hi; base += kCountBlock) {
+    const int64_t p = base + threadIdx.x;
+    const bool deferred = p < hi && key[p] == kDeferred;
+    int v = 0, level = levels - 1;
+    bool got = false;
+    if (deferred) {
+      v = rank[p];
+      const uint32_t m = 1u << (v & 31);
+      for (int l = 0; l < levels - 1 && !got; ++l) {
+        if (!(atomicOr(&bits[l * rg.words + (v >> 5)], m) & m)) {
+          got = true;
+          level = l;
+        }
+      }
+    }
+    const int bucket = static_cast<int>(b) * levels + level;
+    const int slot = wave_slot(deferred && !got, bucket, arrive_count);
+    if (deferred) {
+      key[p] = got ? bucket : -bucket - 1;
+      rank[p] = got ? ((level << kLevelShift) | v) : slot;
+    }
+  }
+  __syncthreads();
   for (int l = threadIdx.x; l < levels; l += kCountBlock) {  // per level: prefix popcounts, stayer count
     int run = 0;
-    for (int w = 0; w < rg.words; ++w) {
-      prefix[l * rg.words + w] = run;
-      run += __popc(bits[l * rg.words + w]);
+    for (int wd = 0; wd < rg.words; ++wd) {
+      prefix[l * rg.words + wd] = run;
+      run += __popc(bits[l * rg.words + wd]);
     }
     stay_count[b * levels + l] = run;
   }
   __syncthreads();
-  for (int64_t base = lo; base < hi; base += kCountBlock) {  // the same thread revisits its own particles
+  for (int64_t base = lo; base < hi; base += kCountBlock) {  // stayer ranks: nodes below it in its level
     const int64_t p = base + threadIdx.x;
     if (p < hi && key[p] >= 0) {
       const int r = rank[p];
@@ -334,7 +374,9 @@ RankGeom rank_geom(const pic_ctx &c) {
     vol *= h.nl[d];
   }
   const int64_t words = (vol + 31) / 32;
-  h.words = (words * c.levels <= kOrderWords && vol < (1 << kLevelShift)) ? static_cast<int>(words) : 0;
+  h.words = (words * c.levels <= kOrderWords && vol < (1 << kLevelShift) && c.levels <= kMaxLevels)
+                ? static_cast<int>(words)
+                : 0;
   return h;
 }
 
