@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(kCountBlock)
   }
   lo = lo < 0 ? 0 : (lo > np ? np : lo);
   hi = hi < lo ? lo : (hi > np ? np : hi);
+  if (lo >= hi) return;  // an empty run: its stayer counts are already zero
   if (order) {
     for (int i = threadIdx.x; i < levels * rg.words; i += kCountBlock) bits[i] = 0u;
     if (threadIdx.x == 0) {  // previous level segments, clamped to partition [lo, hi)

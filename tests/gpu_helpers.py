@@ -13,7 +13,7 @@ import numpy as np
 import oracle as O
 from paper_1503_02464_amd import inputs
 
-# Tolerances.  FP64: the benchmark spec's bound, 1e-12 norm-relative (positions:
+# Tolerances.  FP64: 1e-12 norm-relative (positions:
 # absolute, in cells).  FP32 (one step from an FP32-representable state
 # against the FP64 oracle): a few units of FP32 rounding (2^-24 ~ 6e-8) times
 # the operation depth of each quantity.
