@@ -214,7 +214,7 @@ def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     e, i = w.species()
     npart = e["w"].shape[0] + i["w"].shape[0]
     sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, "fp32", tile=w.tile, slack=1, sort_every=8,
-                     max_particles=e["w"].shape[0], open_x=True, absorb=w.absorb)
+                     max_particles=e["w"].shape[0], open_x=True, absorb=w.absorb, sort_levels=w.sort_levels)
     sim.set_laser(**w.laser())
     for h in (sim.add_species(e), sim.add_species(i)):
         sim.sort(h)  # tiles and levels, then node order (as in build_sim)

@@ -111,6 +111,9 @@ typedef struct {
     int32_t open_x;
     int32_t absorb;        /* cells between each x face and the particle region, >= 2 shape_order + 2,
                               and n[0] >= 2 absorb + 2 (open_x only) */
+    int32_t sort_levels;   /* levels per tile in the sort: particles sharing a nearest node take
+                              distinct levels while they fit (the rest share the last one); 0 means
+                              32, else 2..128; about twice the particles per cell suits */
 } pic_params;
 
 /* A laser injected as a current sheet on the node plane x = plane dx (open

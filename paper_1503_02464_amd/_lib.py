@@ -38,6 +38,7 @@ class Params(ctypes.Structure):
         ("current_accum", ctypes.c_int32),
         ("open_x", ctypes.c_int32),
         ("absorb", ctypes.c_int32),
+        ("sort_levels", ctypes.c_int32),
     ]
 
 

@@ -115,6 +115,7 @@ class LaserFoil:
     tile: tuple = (16, 16, 1)
     seed: int = 1001
     m_ion: float = 1836.0
+    sort_levels: int = 32  # about twice the particles per cell of a species
 
     @property
     def dt(self) -> float:
@@ -164,7 +165,8 @@ def laser_foil_2d(scale: int = 1) -> LaserFoil:
     x0 = 400 // scale
     return LaserFoil(f"laser-foil-2d3v-{2048 // scale}x{1024 // scale}-64ppc-quadratic", 2,
                      (2048 // scale, 1024 // scale, 1), (dx, dx, 1.0), 0.98, 2, 2000, (x0, x0 + max(20 // scale, 2)),
-                     50.0, 64, 0.0, 0.0, 5.0, 4 * lam / scale, 10 * lam, tile=(16, 16, 1), seed=1001)
+                     50.0, 64, 0.0, 0.0, 5.0, 4 * lam / scale, 10 * lam, tile=(16, 16, 1), seed=1001,
+                     sort_levels=128)
 
 
 def laser_foil_3d(scale: int = 1) -> LaserFoil:
@@ -178,7 +180,7 @@ def laser_foil_3d(scale: int = 1) -> LaserFoil:
     return LaserFoil(f"laser-foil-3d3v-{512 // scale}x{256 // scale}x{256 // scale}-16ppc-quadratic", 3,
                      (512 // scale, 256 // scale, 256 // scale), (dx, dx, dx), 0.98, 2, 500,
                      (x0, x0 + max(20 // scale, 2)), 30.0, 16, 0.001, 0.001 / 1836.0, 10.0, 3 * lam / scale,
-                     10 * lam, tile=(8, 8, 8), seed=1003)
+                     10 * lam, tile=(8, 8, 8), seed=1003, sort_levels=32)
 
 
 WORKLOADS = {"uniform-2d-64": uniform_2d_small, "laser-foil-2d": laser_foil_2d, "thermal-3d-256": thermal_3d,

@@ -146,6 +146,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
     return PIC_EINVAL;
   if (p->precision == PIC_FP64 && p->current_accum == PIC_ACC_FP32) return PIC_EINVAL;
   if (p->open_x != 0 && p->open_x != 1) return PIC_EINVAL;
+  if (p->sort_levels != 0 && (p->sort_levels < 2 || p->sort_levels > pic::kMaxSortLevels)) return PIC_EINVAL;
   if (p->open_x && (p->absorb < 2 * p->shape_order + 2 || p->n[0] < 2 * static_cast<int64_t>(p->absorb) + 2))
     return PIC_EINVAL;
   for (int d = 0; d < 3; ++d) {
@@ -182,6 +183,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
     c->ntiles *= c->ntile[d];
   }
   c->elem = p->precision == PIC_FP64 ? 8 : 4;
+  c->levels = p->sort_levels ? p->sort_levels : 32;
   c->acc64 = p->current_accum != PIC_ACC_FP32;
   const size_t jelem = c->acc64 ? 8 : 4;
   // LDS tile geometry: the gather reaches [c-1, c+M] around the particle's
@@ -239,6 +241,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   // bucket starts of the last sort, one slot per species (the next sort's hints)
   w.bucket_start = take(static_cast<size_t>(pic::kMaxSpecies) * (nbuckets + 1) * 4);
   w.scan_partials = take(static_cast<size_t>(pic::sort_scan_blocks(nbuckets)) * 8);
+  w.live_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
   w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
   w.result = take(16 * 8);
   w.rho = take(static_cast<size_t>(ncells) * 8);

@@ -172,6 +172,8 @@ struct TileArgs {
   int rf[3], rj[3];        // LDS field / current box sizes
   int gf_lo[3], gj_lo[3];  // box origins below the tile origin
   int remap;               // 1: spread consecutive tiles over XCDs in blocks
+  const int32_t *live;     // non-empty tiles in order, count at [ntiles] (null: every tile)
+  int64_t ntiles;
   int32_t *stray_count;    // particles left outside their LDS box (handled by k_stragglers)
   int32_t *stray_list;
   int cross_cap;           // entries of the LDS list of wide-window particles
@@ -241,13 +243,22 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *smem = reinterpret_cast<T *>(smem_raw);
   const G geo(t);
+  // Work items are the non-empty tiles (all tiles when no list is known).
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous range of tiles so neighbouring tiles share its L2.
-  int64_t tile = blockIdx.x;
+  // contiguous range of items so neighbouring tiles share its L2, and deal
+  // items, not tile indices, so that a sparse box still spreads over every CU.
+  int64_t items = t.live ? t.live[t.ntiles] : t.ntiles;
+  items = items < 0 ? 0 : (items > t.ntiles ? t.ntiles : items);
+  int64_t item = blockIdx.x;
   if (t.remap) {
-    const int64_t per = gridDim.x / 8;
-    tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+    const int64_t per = (items + 7) / 8;
+    const int64_t j = blockIdx.x / 8;
+    if (j >= per) return;
+    item = (blockIdx.x % 8) * per + j;
   }
+  if (item >= items) return;
+  const int64_t tile = t.live ? t.live[item] : item;
+  if (tile < 0 || tile >= t.ntiles) return;
   // clamp to the species: ranges that a failed sort left beyond np are ignored
   int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
   pbeg = pbeg < 0 ? 0 : (pbeg > s.np ? s.np : pbeg);
@@ -574,7 +585,9 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
     t.gj_lo[d] = c.gj_lo[d];
   }
   t.slack = c.p.slack;
-  t.remap = (c.ntiles % 8 == 0 && c.ntiles >= 64) ? 1 : 0;
+  t.remap = c.ntiles >= 64 ? 1 : 0;
+  t.live = live_tiles(c, sp);
+  t.ntiles = c.ntiles;
   t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
   t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
   t.cross_cap = c.cross_cap;

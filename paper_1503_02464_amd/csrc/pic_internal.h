@@ -15,6 +15,7 @@
 namespace pic {
 
 constexpr int kMaxSpecies = 8;         // species per diagnostics call
+constexpr int kMaxSortLevels = 128;    // largest pic_params.sort_levels
 constexpr int kDiagBlocks = 1024;      // partial sums per species / per grid pass
 constexpr int kDiagSlots = PIC_NDIAG;  // UE UB K Q max|rho| max|G| max|dG| max|cont|
 // Largest capacity of the fused kernel's list of particles that need the
@@ -40,6 +41,8 @@ struct Workspace {
   size_t arrive_count = 0;  // int32[ntiles * levels]: per bucket, the others
   size_t bucket_start = 0;   // int32[kMaxSpecies][nbuckets + 1]: bucket starts of each species' last sort
   size_t scan_partials = 0;  // int64[scan blocks]
+  size_t live_tiles = 0;     // int32[kMaxSpecies][ntiles + 1]: per species slot, the tiles its last sort
+                             // left non-empty, in tile order, then their count
   size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
   size_t result = 0;      // double[16]
   size_t rho = 0;         // double[ncells]
@@ -70,7 +73,7 @@ struct pic_ctx {
   size_t lds_bytes = 0;
   bool acc64 = true;  // LDS current box accumulated in double
   int32_t cross_cap = 0;  // capacity of the fused kernel's wide-window list
-  int32_t levels = 16;  // rank levels per tile in the sort (particles sharing a node go to distinct levels)
+  int32_t levels = 32;  // rank levels per tile in the sort (particles sharing a node go to distinct levels)
   // (tile_start array, particle count) of every species this context sorted
   // (at most kMaxSpecies; entry i owns bucket-start slot i of the workspace):
   // the next sort of that species ranks by the runs tile_start describes
@@ -124,6 +127,9 @@ hipError_t launch_scale_copy(const pic_ctx &c, void *const dst[3], const void *c
 hipError_t launch_particle_adjoint(const pic_ctx &c, const pic_species &sp, const pic_fields &f,
                                    const pic_fields &lam, const pic_species_adjoint &lsp, hipStream_t s);
 hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s);
+// The non-empty tiles of a species' last sort (list, count at [ntiles]), or
+// null when this context has not sorted that species.
+const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp);
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,

@@ -69,7 +69,7 @@ constexpr int kCountBlock = 1024;
 constexpr int64_t kCountChunk = 4096;  // particles per workgroup when not sorted
 // LDS words of the per-level bitmaps over a tile's nodes (and of their prefix
 // counts) that order the particles staying in their tile by node.
-constexpr int kOrderWords = 2048;
+constexpr int kOrderWords = 4096;
 constexpr int kLevelShift = 20;  // stayer rank word: level << 20 | local node
 
 struct RankGeom {
@@ -92,19 +92,27 @@ struct RankGeom {
 //    level did not change keeps its place: the permutation stays close to a
 //    shift, and the scatter's writes stay coalesced.  A particle that left
 //    the tile keeps its level and arrives after the stayers of its new bucket.
-constexpr int kMaxLevels = 64;
+constexpr int kMaxLevels = kMaxSortLevels;
 constexpr int32_t kDeferred = INT32_MIN;  // a stayer whose previous level was taken
 
+struct CountLds {
+  int32_t counter[kRankSlots];
+  uint32_t bits[kOrderWords];
+  int32_t prefix[kOrderWords];
+  int64_t seg[kMaxLevels + 1];
+};
+
+// One run (or chunk) b, by the whole workgroup.
 template <typename T, int M>
-__global__ void __launch_bounds__(kCountBlock)
-    k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w, int open, int64_t np,
-                 SortGeom g, RankGeom rg, int levels, const int32_t *runs, const int32_t *hints, int64_t nruns,
-                 int32_t *key, int32_t *rank, int32_t *stay_count, int32_t *arrive_count) {
-  __shared__ int32_t counter[kRankSlots];
-  __shared__ uint32_t bits[kOrderWords];
-  __shared__ int32_t prefix[kOrderWords];
-  __shared__ int64_t seg[kMaxLevels + 1];
-  const int64_t b = blockIdx.x;
+__device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t *cell, const T *o0, const T *o1,
+                                          const T *o2, const T *w, int open, int64_t np, const SortGeom &g,
+                                          const RankGeom &rg, int levels, const int32_t *runs, const int32_t *hints,
+                                          int64_t nruns, int32_t *key, int32_t *rank, int32_t *stay_count,
+                                          int32_t *arrive_count) {
+  int32_t *counter = sh.counter;
+  uint32_t *bits = sh.bits;
+  int32_t *prefix = sh.prefix;
+  int64_t *seg = sh.seg;
   const bool order = runs != nullptr && hints != nullptr && b < nruns && rg.words > 0;
   int64_t lo, hi;
   if (runs) {  // run b of the previous sort; the extra last workgroup takes any tail
@@ -119,12 +127,12 @@ __global__ void __launch_bounds__(kCountBlock)
   if (lo >= hi) return;  // an empty run: its stayer counts are already zero
   if (order) {
     for (int i = threadIdx.x; i < levels * rg.words; i += kCountBlock) bits[i] = 0u;
-    if (threadIdx.x == 0) {  // previous level segments, clamped to partition [lo, hi)
-      seg[0] = lo;
-      for (int l = 1; l < levels; ++l) {
-        const int64_t h = hints[b * levels + l];
-        seg[l] = h < seg[l - 1] ? seg[l - 1] : (h > hi ? hi : h);
-      }
+    // previous level segments, clamped to partition [lo, hi): the starts are
+    // loaded in parallel, then made monotonic
+    if (threadIdx.x < levels) seg[threadIdx.x] = threadIdx.x == 0 ? lo : hints[b * levels + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int l = 1; l < levels; ++l) seg[l] = seg[l] < seg[l - 1] ? seg[l - 1] : (seg[l] > hi ? hi : seg[l]);
       seg[levels] = hi;
     }
   } else {
@@ -235,6 +243,30 @@ __global__ void __launch_bounds__(kCountBlock)
   }
 }
 
+// One workgroup per run (or chunk).  Runs are taken in the order of the
+// previous sort's list of non-empty tiles: dealing the blocks of a sparse box
+// by tile index would pile the busy ones onto a few XCDs and CUs.
+template <typename T, int M>
+__global__ void __launch_bounds__(kCountBlock)
+    k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w, int open, int64_t np,
+                 SortGeom g, RankGeom rg, int levels, const int32_t *runs, const int32_t *hints, int64_t nruns,
+                 const int32_t *live, int64_t nitems, int32_t *key, int32_t *rank, int32_t *stay_count,
+                 int32_t *arrive_count) {
+  __shared__ CountLds sh;
+  int64_t b = blockIdx.x;
+  if (live) {  // the previous sort's non-empty runs first (balanced over the CUs), then the tail
+    int64_t nlive = live[nruns];
+    nlive = nlive < 0 ? 0 : (nlive > nruns ? nruns : nlive);
+    if (b > nlive) return;
+    b = b < nlive ? live[b] : nruns;
+    if (b < 0 || b > nruns) return;
+  } else if (b >= nitems) {
+    return;
+  }
+  count_run<T, M>(b, sh, cell, o0, o1, o2, w, open, np, g, rg, levels, runs, hints, nruns, key, rank, stay_count,
+                  arrive_count);
+}
+
 // Multi-block exclusive scan of n counters into start[0..n]; every `levels`
 // entries the running offset is also the start of a tile.
 constexpr int kScanBlock = 1024;
@@ -319,6 +351,24 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *ca, co
     start[n] = static_cast<int32_t>(run);
 }
 
+// The tiles left non-empty, in tile order, and their count at [ntiles]: each
+// thread counts a contiguous chunk, one block scan places the chunks.
+__global__ void __launch_bounds__(kScanBlock) k_list_tiles(const int32_t *tile_start, int64_t ntiles,
+                                                          int32_t *live) {
+  __shared__ int64_t sh[kScanBlock];
+  const int64_t per = (ntiles + kScanBlock - 1) / kScanBlock;
+  const int64_t a = threadIdx.x * per;
+  const int64_t e = a + per < ntiles ? a + per : ntiles;
+  int64_t cnt = 0;
+#pragma unroll 8
+  for (int64_t t = a; t < e; ++t) cnt += tile_start[t + 1] > tile_start[t] ? 1 : 0;
+  int64_t total;
+  int64_t pos = block_exclusive_scan(cnt, sh, total);
+  for (int64_t t = a; t < e; ++t)
+    if (tile_start[t + 1] > tile_start[t]) live[pos++] = static_cast<int32_t>(t);
+  if (threadIdx.x == 0) live[ntiles] = static_cast<int32_t>(total);
+}
+
 // Pass 3.  A stayer goes to start[bucket] + its node rank, an arrival after
 // the bucket's stayers.
 template <typename T, int D>
@@ -383,7 +433,7 @@ RankGeom rank_geom(const pic_ctx &c) {
 
 template <typename T>
 void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_runs, const int32_t *hints,
-           hipStream_t s) {
+           const int32_t *live, hipStream_t s) {
   const auto *o0 = static_cast<const T *>(sp.off[0]);
   const auto *o1 = static_cast<const T *>(sp.off[1]);
   const auto *o2 = static_cast<const T *>(c.p.dims == 3 ? sp.off[2] : sp.off[0]);
@@ -393,16 +443,19 @@ void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_r
   int32_t *arrive = c.wsp<int32_t>(c.ws.arrive_count);
   const int32_t *runs = by_runs ? sp.tile_start : nullptr;
   const int64_t nruns = by_runs ? c.ntiles : 0;
-  const unsigned blocks = static_cast<unsigned>(by_runs ? c.ntiles + 1 : (sp.np + kCountChunk - 1) / kCountChunk);
+  const int64_t items = by_runs ? c.ntiles + 1 : (sp.np + kCountChunk - 1) / kCountChunk;
+  const unsigned blocks = static_cast<unsigned>(items);
   const RankGeom rg = rank_geom(c);
   const auto *w = static_cast<const T *>(sp.w);
   const int open = c.p.open_x;
   if (c.p.shape_order == 2)
     hipLaunchKernelGGL((k_sort_count<T, 2>), dim3(blocks), dim3(kCountBlock), 0, s, sp.cell, o0, o1, o2, w, open,
-                       sp.np, g, rg, c.levels, runs, hints, nruns, keys, ranks, stay, arrive);
+                       sp.np, g, rg, c.levels, runs, hints, nruns, by_runs ? live : nullptr, items, keys, ranks, stay,
+                       arrive);
   else
     hipLaunchKernelGGL((k_sort_count<T, 1>), dim3(blocks), dim3(kCountBlock), 0, s, sp.cell, o0, o1, o2, w, open,
-                       sp.np, g, rg, c.levels, runs, hints, nruns, keys, ranks, stay, arrive);
+                       sp.np, g, rg, c.levels, runs, hints, nruns, by_runs ? live : nullptr, items, keys, ranks, stay,
+                       arrive);
 }
 
 template <typename T, int D>
@@ -453,6 +506,7 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
     }
   }
   int32_t *start = c.wsp<int32_t>(c.ws.bucket_start) + static_cast<size_t>(slot) * (nb + 1);
+  int32_t *live = c.wsp<int32_t>(c.ws.live_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
   if (sp.np > 0) {
     SortGeom g{};
     g.bits0 = c.bits[0];
@@ -469,9 +523,9 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
     g.dims = c.p.dims;
     const int32_t *hints = by_runs ? start : nullptr;
     if (c.p.precision == PIC_FP64)
-      count<double>(c, sp, g, by_runs, hints, s);
+      count<double>(c, sp, g, by_runs, hints, live, s);
     else
-      count<float>(c, sp, g, by_runs, hints, s);
+      count<float>(c, sp, g, by_runs, hints, live, s);
   }
   const int64_t nblk = sort_scan_blocks(nb);
   int64_t *partials = c.wsp<int64_t>(c.ws.scan_partials);
@@ -480,6 +534,7 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_partials_top, dim3(1), dim3(kScanBlock), 0, s, partials, nblk);
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, stay, arrive, nb,
                      partials, c.levels, start, sp.tile_start, c.ntiles);
+  hipLaunchKernelGGL(k_list_tiles, dim3(1), dim3(kScanBlock), 0, s, sp.tile_start, c.ntiles, live);
   if (sp.np > 0) {
     const bool f64 = c.p.precision == PIC_FP64;
     if (f64)
@@ -499,6 +554,13 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
   sp.sorted = 1;
   c.sorted_runs[slot].second = sp.np;
   return hipSuccess;
+}
+
+const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp) {
+  for (size_t i = 0; i < c.sorted_runs.size(); ++i)
+    if (c.sorted_runs[i].first == sp.tile_start && c.sorted_runs[i].second == sp.np)
+      return c.wsp<int32_t>(c.ws.live_tiles) + i * (c.ntiles + 1);
+  return nullptr;
 }
 
 }  // namespace pic

@@ -70,11 +70,13 @@ class Simulation:
     per sort tile; slack guard cells; sort_every steps between sorts;
     current_accum the LDS current accumulation type ("auto" = fp64); open_x
     opens the x faces (Mur fields, particles removed outside
-    [absorb, n0 - absorb) cells)."""
+    [absorb, n0 - absorb) cells); sort_levels the levels per tile of the sort
+    (0: the library's default)."""
 
     def __init__(self, dims: int, n: tuple, dx: tuple, dt: float, order: int, precision: str = "fp32",
                  tile: tuple = (8, 8, 8), slack: int = 1, sort_every: int = 4, max_particles: int = 0,
-                 current_accum: str = "auto", open_x: bool = False, absorb: int = 0, device: str = "cuda"):
+                 current_accum: str = "auto", open_x: bool = False, absorb: int = 0, sort_levels: int = 0,
+                 device: str = "cuda"):
         self.lib = L.load()
         self.dims = dims
         self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
@@ -101,6 +103,7 @@ class Simulation:
         p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64}[current_accum]
         p.open_x = 1 if open_x else 0
         p.absorb = int(absorb)
+        p.sort_levels = int(sort_levels)
         self.open_x = bool(open_x)
         self.absorb = int(absorb)
         self.params = p

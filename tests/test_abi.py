@@ -17,7 +17,7 @@ def lib():
 
 
 def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec=L.PIC_FP32, tile=(8, 8, 8),
-           slack=1, sort_every=4, maxp=1000, acc=L.PIC_ACC_AUTO, open_x=0, absorb=0):
+           slack=1, sort_every=4, maxp=1000, acc=L.PIC_ACC_AUTO, open_x=0, absorb=0, sort_levels=0):
     p = L.Params()
     p.dims = dims
     p.n = L._c3i(*n)
@@ -32,6 +32,7 @@ def params(dims=3, n=(16, 16, 16), dx=(0.05, 0.05, 0.05), cfl=0.7, order=2, prec
     p.current_accum = acc
     p.open_x = open_x
     p.absorb = absorb
+    p.sort_levels = sort_levels
     return p
 
 
@@ -84,6 +85,7 @@ def test_cfl_limit(lib, cfl, want):
     dict(acc=3), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32),
     dict(open_x=2), dict(open_x=1, absorb=5),  # absorb below 2 * order + 2
     dict(open_x=1, absorb=8),  # n[0] < 2 * absorb + 2
+    dict(sort_levels=1), dict(sort_levels=129),
 ])
 def test_invalid_params(lib, kw):
     st, ctx = init(lib, params(**kw))

@@ -27,7 +27,7 @@ def ora_grid(w):
 
 def make(w, prec, max_particles, sort_every=4):
     return Simulation(w.dims, w.n, w.dx, w.dt, w.order, prec, tile=w.tile, slack=1, sort_every=sort_every,
-                      max_particles=max_particles, open_x=True, absorb=w.absorb)
+                      max_particles=max_particles, open_x=True, absorb=w.absorb, sort_levels=w.sort_levels)
 
 
 def ora_laser(w):
