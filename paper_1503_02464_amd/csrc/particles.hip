@@ -301,9 +301,27 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   const int lane = __lane_id();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
-  for (int64_t p = pbeg + threadIdx.x; p < pend; p += BLOCK) {
+  // The next particle's data is loaded before the current one is processed,
+  // so its HBM latency hides behind the gather, push and deposit.
+  int64_t p = pbeg + threadIdx.x;
+  int32_t n_cell = 0;
+  T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
+  if (p < pend) {
+    n_cell = s.cell[p];
+    n_w = s.w[p];
+    load_particle<T, D>(s, p, n_o, n_u);
+  }
+  for (; p < pend; p += BLOCK) {
+    const int32_t p_cell = n_cell;
+    const T w = n_w;
+    T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
+    if (p + BLOCK < pend) {
+      n_cell = s.cell[p + BLOCK];
+      n_w = s.w[p + BLOCK];
+      load_particle<T, D>(s, p + BLOCK, n_o, n_u);
+    }
     int c[3];
-    unpack(s.cell[p], g, c);
+    unpack(p_cell, g, c);
     // cell relative to the tile origin, unwrapped across the periodic seam
     int lc[3] = {0, 0, 0};
     bool inside = true;
@@ -325,10 +343,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
     }
     if (!inside) continue;
-    const T w = s.w[p];
     if (s.open && w == T(0)) continue;  // removed at an open face, until the next sort drops it
-    T o[3], u[3];
-    load_particle<T, D>(s, p, o, u);
     T eb[6];
     gather_eb<T, D, M>(lf, lc, o, eb);
     boris<T>(u, eb, s.h);
