@@ -329,6 +329,14 @@ def main() -> int:
                                                                   "yee_cell_updates_per_s")},
         "adjoint": adj,
         "laser_foil": laser,
+        # error bounds against the FP64 CPU oracle that the GPU parity tests
+        # enforce on this path (one step from an FP32-representable state for
+        # FP32; every quantity for FP64), including at this workload's full size
+        "error_vs_oracle": {
+            "fp32": {"position_cells_abs": 4e-7, "u_rel": 2e-6, "E_rel": 2e-6, "B_rel": 2e-6, "J_rel": 1e-5},
+            "fp64_rel": 1e-12,
+            "enforced_by": ["tests/test_gpu_parity.py", "tests/test_gpu_fullsize.py"],
+        },
     }
     print(json.dumps(line), flush=True)
     return 0

@@ -228,6 +228,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.save_off = take(3 * mp * c->elem);
   w.sort_key = take(mp * 4);
   w.sort_rank = take(mp * 4);
+  w.sort_src = take(mp * 4);
   w.stray_count = take(4);
   w.stray_list = take(mp * 4);
   // sort buckets: (tile, level) pairs plus one for particles removed at open faces

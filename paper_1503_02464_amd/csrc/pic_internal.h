@@ -35,6 +35,7 @@ struct Workspace {
   size_t save_off = 0;    // T[3][max_particles]: offsets at x^n (unfused path)
   size_t sort_key = 0;    // int32[max_particles]
   size_t sort_rank = 0;   // int32[max_particles]
+  size_t sort_src = 0;    // int32[max_particles]: the particle each sorted slot takes
   size_t stray_count = 0; // int32: particles the tiled kernel left outside their LDS box
   size_t stray_list = 0;  // int32[max_particles]: their indices
   size_t stay_count = 0;    // int32[ntiles * levels]: per (tile, level) bucket, particles that stayed in the tile

@@ -10,8 +10,8 @@
 // one tile (or per fixed chunk when the species is not sorted yet) assigns
 // levels and ranks with LDS counters and bitmaps (see k_sort_count); (2) an
 // exclusive scan of the bucket counts (multi-block) gives the bucket starts
-// and the tile starts; (3) every particle is copied to its slot in the
-// second set.  Particles removed at an open face go to one last bucket behind
+// and the tile starts; (3) every particle's slot is found, then every array
+// is copied into the second set in slot order.  Particles removed at an open face go to one last bucket behind
 // every tile.
 #include <hip/hip_runtime.h>
 
@@ -369,16 +369,11 @@ __global__ void __launch_bounds__(kScanBlock) k_list_tiles(const int32_t *tile_s
   if (threadIdx.x == 0) live[ntiles] = static_cast<int32_t>(total);
 }
 
-// Pass 3.  A stayer goes to start[bucket] + its node rank, an arrival after
-// the bucket's stayers.
-template <typename T, int D>
-__global__ void __launch_bounds__(256) k_sort_scatter(int64_t np, const int32_t *key, const int32_t *rank,
-                                                      const int32_t *start, const int32_t *stay,
-                                                      const int32_t *cell, const T *o0,
-                                                      const T *o1, const T *o2, const T *u0, const T *u1,
-                                                      const T *u2, const T *w, int32_t *cell_d, T *o0d, T *o1d,
-                                                      T *o2d, T *u0d, T *u1d, T *u2d, T *wd, int64_t nbuckets,
-                                                      int32_t *flags) {
+// Pass 3a.  Each particle's slot: a stayer goes to start[bucket] + its node
+// rank, an arrival after the bucket's stayers.  src[slot] = particle.
+__global__ void __launch_bounds__(256) k_sort_slots(int64_t np, const int32_t *key, const int32_t *rank,
+                                                   const int32_t *start, const int32_t *stay, int64_t nbuckets,
+                                                   int32_t *src, int32_t *flags) {
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= np) return;
   const int32_t k = key[p];
@@ -390,6 +385,21 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int64_t np, const int32_t 
     atomicOr(&flags[0], kFlagSort);
     return;
   }
+  src[q] = static_cast<int32_t>(p);
+}
+
+// Pass 3b.  Every array is copied into the second set in destination order
+// (coalesced writes; the reads follow the permutation, which keeps most
+// neighbours together).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_sort_gather(int64_t np, const int32_t *src, const int32_t *cell,
+                                                    const T *o0, const T *o1, const T *o2, const T *u0, const T *u1,
+                                                    const T *u2, const T *w, int32_t *cell_d, T *o0d, T *o1d,
+                                                    T *o2d, T *u0d, T *u1d, T *u2d, T *wd) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= np) return;
+  const int64_t p = src[q];
+  if (p < 0 || p >= np) return;  // only after a flagged inconsistency
   cell_d[q] = cell[p];
   o0d[q] = o0[p];
   o1d[q] = o1[p];
@@ -461,15 +471,18 @@ void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_r
 template <typename T, int D>
 void scatter(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
-  hipLaunchKernelGGL((k_sort_scatter<T, D>), dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
-                     c.wsp<int32_t>(c.ws.sort_rank), start, c.wsp<int32_t>(c.ws.stay_count), sp.cell,
+  int32_t *src = c.wsp<int32_t>(c.ws.sort_src);
+  hipLaunchKernelGGL(k_sort_slots, dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
+                     c.wsp<int32_t>(c.ws.sort_rank), start, c.wsp<int32_t>(c.ws.stay_count),
+                     c.ntiles * c.levels + 1, src, c.wsp<int32_t>(c.ws.flags));
+  hipLaunchKernelGGL((k_sort_gather<T, D>), dim3(blocks), dim3(256), 0, s, sp.np, src, sp.cell,
                      static_cast<const T *>(sp.off[0]), static_cast<const T *>(sp.off[1]),
                      static_cast<const T *>(sp.off[2]), static_cast<const T *>(sp.u[0]),
                      static_cast<const T *>(sp.u[1]), static_cast<const T *>(sp.u[2]),
                      static_cast<const T *>(sp.w), sp.cell_alt, static_cast<T *>(sp.off_alt[0]),
                      static_cast<T *>(sp.off_alt[1]), static_cast<T *>(sp.off_alt[2]),
                      static_cast<T *>(sp.u_alt[0]), static_cast<T *>(sp.u_alt[1]), static_cast<T *>(sp.u_alt[2]),
-                     static_cast<T *>(sp.w_alt), c.ntiles * c.levels + 1, c.wsp<int32_t>(c.ws.flags));
+                     static_cast<T *>(sp.w_alt));
 }
 
 }  // namespace

@@ -197,3 +197,40 @@ def test_sort_moves_removed_particles_behind_the_tiles():
     s.step(1)  # removed particles stay out of every tile
     s.check()
     s.close()
+
+
+def test_every_particle_leaves():
+    """A species that entirely leaves through the faces: nothing stays live,
+    the current after that step is the laser sheet alone, the sort moves every
+    particle behind the tiles, and later steps run on an empty species."""
+    g = open_grid(2, 2)
+    n0 = g.n[0]
+    npart = 64
+    sp = {"q": -1.0, "m": 1.0, "cell": np.zeros((3, npart), np.int32), "off": np.full((3, npart), 0.02),
+          "u": np.zeros((3, npart)), "w": np.full(npart, 1e-3)}
+    half = npart // 2
+    sp["cell"][0, :half] = ABSORB  # first live cell, heading out through the low face
+    sp["cell"][0, half:] = n0 - ABSORB - 1  # last live cell, heading out through the high face
+    sp["off"][0, half:] = 0.98
+    r = inputs.rng(460)
+    sp["cell"][1] = r.integers(0, g.n[1], npart)
+    sp["off"][1] = r.random(npart)
+    sp["u"][0, :half] = -0.9
+    sp["u"][0, half:] = 0.9
+    sp["u"][1] = r.normal(0, 0.2, npart)  # so that the current, and B, vary in y
+    s = open_sim(g, "fp64", sort_every=1 << 30, max_particles=npart)
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    assert int(s.live(h).sum().item()) == 0
+    ref_f = O.new_fields(g)
+    ref, bad, removed = O.step_open(g, ref_f, [O.copy_species(sp)], ABSORB, n0 - ABSORB, None, 0)
+    assert bad == 0 and removed == npart and ref[0]["w"].shape[0] == 0
+    compare_fields("fp64", s.get_fields(), ref_f, what="all leave")
+    s.sort(h)
+    assert s.tile_start(h)[-1] == 0
+    s.step(3)
+    s.check()
+    d = s.diagnostics()
+    assert d["Q"] == 0.0 and d["K"] == 0.0
+    s.close()
