@@ -176,6 +176,7 @@ struct TileArgs {
   int64_t ntiles;
   int32_t *stray_count;    // particles left outside their LDS box (handled by k_stragglers)
   int32_t *stray_list;
+  int32_t *queue;          // [8]: next item of each XCD's range, zero at launch
   int cross_cap;           // entries of the LDS list of wide-window particles
 };
 
@@ -232,11 +233,11 @@ struct CurrentBox<T, RuntimeGeom, DD> {
   }
 };
 
-// One workgroup per tile of sorted particles: stage E and B of the tile plus
-// guards in LDS, push every particle whose cell lies within the slack of
-// the tile (gather from LDS, Boris, move, Esirkepov into an LDS current box
-// held in TJ), then add the current box into J in HBM.  Particles further
-// out are listed for k_stragglers.
+// Persistent workgroups, each taking one tile of sorted particles at a time:
+// stage E and B of the tile plus guards in LDS, push every particle whose
+// cell lies within the slack of the tile (gather from LDS, Boris, move,
+// Esirkepov into an LDS current box held in TJ), then add the current box
+// into J in HBM.  Particles further out are listed for k_stragglers.
 template <typename T, int D, int M, class G, int BLOCK, typename TJ>
 __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                               GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
@@ -244,30 +245,21 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   T *smem = reinterpret_cast<T *>(smem_raw);
   const G geo(t);
   // Work items are the non-empty tiles (all tiles when no list is known).
-  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
-  // contiguous range of items so neighbouring tiles share its L2, and deal
-  // items, not tile indices, so that a sparse box still spreads over every CU.
+  // Workgroups are dealt to the 8 XCDs round-robin.  Each XCD owns a
+  // contiguous range of items, so that neighbouring tiles share its L2.  A
+  // workgroup's first item is the j-th of its XCD's range (j = its index
+  // among that XCD's workgroups), which spreads a sparse box over every CU;
+  // items beyond the first round come from the XCD's queue, and a workgroup
+  // whose queue is empty takes from the next ones.
   int64_t items = t.live ? t.live[t.ntiles] : t.ntiles;
   items = items < 0 ? 0 : (items > t.ntiles ? t.ntiles : items);
-  int64_t item = blockIdx.x;
-  if (t.remap) {
-    const int64_t per = (items + 7) / 8;
-    const int64_t j = blockIdx.x / 8;
-    if (j >= per) return;
-    item = (blockIdx.x % 8) * per + j;
-  }
-  if (item >= items) return;
-  const int64_t tile = t.live ? t.live[item] : item;
-  if (tile < 0 || tile >= t.ntiles) return;
-  // clamp to the species: ranges that a failed sort left beyond np are ignored
-  int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
-  pbeg = pbeg < 0 ? 0 : (pbeg > s.np ? s.np : pbeg);
-  pend = pend > s.np ? s.np : pend;
-  if (pbeg >= pend) return;
-  const int tx = static_cast<int>(tile % t.ntile[0]);
-  const int ty = static_cast<int>((tile / t.ntile[0]) % t.ntile[1]);
-  const int tz = static_cast<int>(tile / ((int64_t)t.ntile[0] * t.ntile[1]));
-  const int T0[3] = {tx * geo.L0, ty * geo.L1, tz * geo.L2};
+  const int nq = t.remap ? 8 : 1;
+  const int64_t per = (items + nq - 1) / nq;
+  const int home = static_cast<int>(blockIdx.x % nq);
+  // the first item, and the workgroups per XCD (the items dealt before any queue)
+  int64_t first = static_cast<int64_t>(blockIdx.x / nq);
+  first = first < per && home * per + first < items ? home * per + first : -1;
+  const int64_t nb = gridDim.x;
 
   T *fl = smem;
   TJ *jl = reinterpret_cast<TJ *>(smem + 6 * geo.FVOL);  // 6 * FVOL * sizeof(T) is a multiple of 8
@@ -278,159 +270,192 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   T *xw = xo + 6 * CAP;                               // [2][CAP]: weight, 2D v_z factor
   int32_t *xk = reinterpret_cast<int32_t *>(xw + 2 * CAP);  // [CAP]: local cell and cell change
   int32_t *xn = xk + CAP;                                    // list length
-  if (threadIdx.x == 0) *xn = 0;
-
-  // stage E, B of the tile plus guards (periodic wrap)
-  for (int idx = threadIdx.x; idx < geo.FVOL; idx += BLOCK) {
-    const int li = idx % geo.FX;
-    const int lj = (idx / geo.FX) % geo.FY;
-    const int lk = idx / (geo.FX * geo.FY);
-    const int gi = wrap_full(T0[0] - geo.FLO + li, g.n[0]);
-    const int gjj = wrap_full(T0[1] - geo.FLO + lj, g.n[1]);
-    const int gk = D == 3 ? wrap_full(T0[2] - geo.FLO + lk, g.n[2]) : 0;
-    const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) fl[c * geo.FVOL + idx] = gf.F[c][gidx];
-  }
+  int32_t *slot = xn + 1;                                    // the item this workgroup takes next
+  // the merge clears the box behind it, so it is zeroed once here
   for (int idx = threadIdx.x; idx < 3 * geo.JVOL; idx += BLOCK) jl[idx] = TJ(0);
-  __syncthreads();
 
-  // local frames: the tile origin is (0,0,0)
-  const auto lf = FieldBox<T, G, D>::make(fl, geo);
-  const auto lj = CurrentBox<TJ, G, D>::make(jl, geo);
-  const int lane = __lane_id();
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int round = 0;; ++round) {
+    if (threadIdx.x == 0) {
+      int64_t it = round == 0 ? first : -1;
+      for (int k = 0; k < nq && it < 0; ++k) {
+        const int q = (home + k) % nq;
+        const int64_t lo = q * per, hi = lo + per < items ? lo + per : items;
+        const int64_t dealt = (nb - q + nq - 1) / nq;  // items of queue q taken in the first round
+        if (lo + dealt >= hi) continue;
+        const int64_t v = atomicAdd(&t.queue[q], 1);
+        if (lo + dealt + v < hi) it = lo + dealt + v;
+      }
+      *slot = static_cast<int32_t>(it);
+      *xn = 0;
+    }
+    __syncthreads();
+    const int64_t item = *slot;
+    __syncthreads();  // every thread has its item before thread 0 writes the next one
+    if (item < 0) break;
+    const int64_t tile = t.live ? t.live[item] : item;
+    if (tile < 0 || tile >= t.ntiles) continue;
+    // clamp to the species: ranges that a failed sort left beyond np are ignored
+    int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
+    pbeg = pbeg < 0 ? 0 : (pbeg > s.np ? s.np : pbeg);
+    pend = pend > s.np ? s.np : pend;
+    if (pbeg >= pend) continue;
+    const int tx = static_cast<int>(tile % t.ntile[0]);
+    const int ty = static_cast<int>((tile / t.ntile[0]) % t.ntile[1]);
+    const int tz = static_cast<int>(tile / ((int64_t)t.ntile[0] * t.ntile[1]));
+    const int T0[3] = {tx * geo.L0, ty * geo.L1, tz * geo.L2};
 
-  // The next particle's data is loaded before the current one is processed,
-  // so its HBM latency hides behind the gather, push and deposit.
-  int64_t p = pbeg + threadIdx.x;
-  int32_t n_cell = 0;
-  T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
-  if (p < pend) {
-    n_cell = s.cell[p];
-    n_w = s.w[p];
-    load_particle<T, D>(s, p, n_o, n_u);
-  }
-  for (; p < pend; p += BLOCK) {
-    const int32_t p_cell = n_cell;
-    const T w = n_w;
-    T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
-    if (p + BLOCK < pend) {
-      n_cell = s.cell[p + BLOCK];
-      n_w = s.w[p + BLOCK];
-      load_particle<T, D>(s, p + BLOCK, n_o, n_u);
-    }
-    int c[3];
-    unpack(p_cell, g, c);
-    // cell relative to the tile origin, unwrapped across the periodic seam
-    int lc[3] = {0, 0, 0};
-    bool inside = true;
+    // stage E, B of the tile plus guards (periodic wrap)
+    for (int idx = threadIdx.x; idx < geo.FVOL; idx += BLOCK) {
+      const int li = idx % geo.FX;
+      const int lj = (idx / geo.FX) % geo.FY;
+      const int lk = idx / (geo.FX * geo.FY);
+      const int gi = wrap_full(T0[0] - geo.FLO + li, g.n[0]);
+      const int gjj = wrap_full(T0[1] - geo.FLO + lj, g.n[1]);
+      const int gk = D == 3 ? wrap_full(T0[2] - geo.FLO + lk, g.n[2]) : 0;
+      const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int l = c[d] - T0[d];
-      if (l > g.n[d] / 2) l -= g.n[d];
-      if (l < -g.n[d] / 2) l += g.n[d];
-      lc[d] = l;
-      const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
-      inside = inside && (l >= -geo.S) && (l < L + geo.S);
+      for (int c = 0; c < 6; ++c) fl[c * geo.FVOL + idx] = gf.F[c][gidx];
     }
-    const uint64_t out = __ballot(!inside);
-    if (out) {  // list the particles outside the box for the HBM path
-      const int leader = __ffsll(static_cast<unsigned long long>(out)) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(t.stray_count, __popcll(out));
-      base = __shfl(base, leader);
-      if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
+    __syncthreads();
+
+    // local frames: the tile origin is (0,0,0)
+    const auto lf = FieldBox<T, G, D>::make(fl, geo);
+    const auto lj = CurrentBox<TJ, G, D>::make(jl, geo);
+    const int lane = __lane_id();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+    // The next particle's data is loaded before the current one is processed,
+    // so its HBM latency hides behind the gather, push and deposit.
+    int64_t p = pbeg + threadIdx.x;
+    int32_t n_cell = 0;
+    T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
+    if (p < pend) {
+      n_cell = s.cell[p];
+      n_w = s.w[p];
+      load_particle<T, D>(s, p, n_o, n_u);
     }
-    if (!inside) continue;
-    if (s.open && w == T(0)) continue;  // removed at an open face, until the next sort drops it
-    T eb[6];
-    gather_eb<T, D, M>(lf, lc, o, eb);
-    boris<T>(u, eb, s.h);
-    const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    T on[3] = {T(0), T(0), T(0)};
-    int dc[3] = {0, 0, 0};
-    const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
-    if (!ok) atomicOr(&flags[0], kFlagCross);
-    const T jz = D == 2 ? s.jz * u[2] * ig : T(0);
-    const bool wide = ok && crosses<T, D, M>(o, dc, on);
-    if (ok && !wide) {
-      Esirk<T, M> e;
-      esirkepov_factors<T, D, M>(o, dc, on, e);
-      const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-      esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
-    }
-    // one LDS atomic per wavefront reserves list slots for the wide ones
-    const uint64_t wm = __ballot(wide);
-    if (wm) {
-      const int leader = __ffsll(static_cast<unsigned long long>(wm)) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(xn, __popcll(wm));
-      base = __shfl(base, leader);
-      if (wide) {
-        const int k = base + __popcll(wm & below);
-        if (k < CAP) {
+    for (; p < pend; p += BLOCK) {
+      const int32_t p_cell = n_cell;
+      const T w = n_w;
+      T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
+      if (p + BLOCK < pend) {
+        n_cell = s.cell[p + BLOCK];
+        n_w = s.w[p + BLOCK];
+        load_particle<T, D>(s, p + BLOCK, n_o, n_u);
+      }
+      int c[3];
+      unpack(p_cell, g, c);
+      // cell relative to the tile origin, unwrapped across the periodic seam
+      int lc[3] = {0, 0, 0};
+      bool inside = true;
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            xo[d * CAP + k] = o[d];
-            xo[(3 + d) * CAP + k] = on[d];
+      for (int d = 0; d < D; ++d) {
+        int l = c[d] - T0[d];
+        if (l > g.n[d] / 2) l -= g.n[d];
+        if (l < -g.n[d] / 2) l += g.n[d];
+        lc[d] = l;
+        const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
+        inside = inside && (l >= -geo.S) && (l < L + geo.S);
+      }
+      const uint64_t out = __ballot(!inside);
+      if (out) {  // list the particles outside the box for the HBM path
+        const int leader = __ffsll(static_cast<unsigned long long>(out)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(t.stray_count, __popcll(out));
+        base = __shfl(base, leader);
+        if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
+      }
+      if (!inside) continue;
+      if (s.open && w == T(0)) continue;  // removed at an open face, until the next sort drops it
+      T eb[6];
+      gather_eb<T, D, M>(lf, lc, o, eb);
+      boris<T>(u, eb, s.h);
+      const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+      T on[3] = {T(0), T(0), T(0)};
+      int dc[3] = {0, 0, 0};
+      const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
+      if (!ok) atomicOr(&flags[0], kFlagCross);
+      const T jz = D == 2 ? s.jz * u[2] * ig : T(0);
+      const bool wide = ok && crosses<T, D, M>(o, dc, on);
+      if (ok && !wide) {
+        Esirk<T, M> e;
+        esirkepov_factors<T, D, M>(o, dc, on, e);
+        const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+        esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
+      }
+      // one LDS atomic per wavefront reserves list slots for the wide ones
+      const uint64_t wm = __ballot(wide);
+      if (wm) {
+        const int leader = __ffsll(static_cast<unsigned long long>(wm)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(xn, __popcll(wm));
+        base = __shfl(base, leader);
+        if (wide) {
+          const int k = base + __popcll(wm & below);
+          if (k < CAP) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              xo[d * CAP + k] = o[d];
+              xo[(3 + d) * CAP + k] = on[d];
+            }
+            xw[k] = w;
+            xw[CAP + k] = jz;
+            xk[k] = pack_local(lc, dc);
+          } else {  // list full: deposit here
+            Esirk<T, M> e;
+            esirkepov_factors<T, D, M>(o, dc, on, e);
+            const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+            esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * jz);
           }
-          xw[k] = w;
-          xw[CAP + k] = jz;
-          xk[k] = pack_local(lc, dc);
-        } else {  // list full: deposit here
-          Esirk<T, M> e;
-          esirkepov_factors<T, D, M>(o, dc, on, e);
-          const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-          esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * jz);
         }
       }
-    }
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-      s.off[d][p] = on[d];
+      for (int d = 0; d < D; ++d) {
+        c[d] = wrap_near(c[d] + dc[d], g.n[d]);
+        s.off[d][p] = on[d];
+      }
+      s.cell[p] = pack(c, g);
+      s.u[0][p] = u[0];
+      s.u[1][p] = u[1];
+      s.u[2][p] = u[2];
+      absorb_if_out(s, p, c[0]);
     }
-    s.cell[p] = pack(c, g);
-    s.u[0][p] = u[0];
-    s.u[1][p] = u[1];
-    s.u[2][p] = u[2];
-    absorb_if_out(s, p, c[0]);
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // the listed particles, with every lane busy
-  const int nx = *xn < CAP ? *xn : CAP;
-  for (int k = threadIdx.x; k < nx; k += BLOCK) {
-    T o0[3], o1[3];
-    int lc[3], dc[3];
+    // the listed particles, with every lane busy
+    const int nx = *xn < CAP ? *xn : CAP;
+    for (int k = threadIdx.x; k < nx; k += BLOCK) {
+      T o0[3], o1[3];
+      int lc[3], dc[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      o0[d] = xo[d * CAP + k];
-      o1[d] = xo[(3 + d) * CAP + k];
+      for (int d = 0; d < 3; ++d) {
+        o0[d] = xo[d * CAP + k];
+        o1[d] = xo[(3 + d) * CAP + k];
+      }
+      unpack_local(xk[k], lc, dc);
+      const T w = xw[k];
+      Esirk<T, M> e;
+      esirkepov_factors<T, D, M>(o0, dc, o1, e);
+      const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+      esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
     }
-    unpack_local(xk[k], lc, dc);
-    const T w = xw[k];
-    Esirk<T, M> e;
-    esirkepov_factors<T, D, M>(o0, dc, o1, e);
-    const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-    esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // add the current box into HBM (skipping cells nothing touched)
-  for (int idx = threadIdx.x; idx < geo.JVOL; idx += BLOCK) {
-    const int li = idx % geo.JX;
-    const int lj2 = (idx / geo.JX) % geo.JY;
-    const int lk = idx / (geo.JX * geo.JY);
-    const int gi = wrap_full(T0[0] - geo.JLO + li, g.n[0]);
-    const int gjj = wrap_full(T0[1] - geo.JLO + lj2, g.n[1]);
-    const int gk = D == 3 ? wrap_full(T0[2] - geo.JLO + lk, g.n[2]) : 0;
-    const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
+    // add the current box into HBM (skipping cells nothing touched)
+    for (int idx = threadIdx.x; idx < geo.JVOL; idx += BLOCK) {
+      const int li = idx % geo.JX;
+      const int lj2 = (idx / geo.JX) % geo.JY;
+      const int lk = idx / (geo.JX * geo.JY);
+      const int gi = wrap_full(T0[0] - geo.JLO + li, g.n[0]);
+      const int gjj = wrap_full(T0[1] - geo.JLO + lj2, g.n[1]);
+      const int gk = D == 3 ? wrap_full(T0[2] - geo.JLO + lk, g.n[2]) : 0;
+      const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
-      if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
+      for (int c = 0; c < 3; ++c) {
+        const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
+        jl[c * geo.JVOL + idx] = TJ(0);  // ready for the next tile
+        if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
+      }
     }
   }
 }
@@ -568,7 +593,16 @@ hipError_t launch_tiled_acc(const pic_ctx &c, const pic_species &sp, const pic_f
     if (e != hipSuccess) return e;
     lds_set = lds;
   }
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(c.ntiles)), dim3(BLOCK), lds, st, species_args<T>(c, sp),
+  // persistent workgroups: as many as the device holds at once, at most one per tile
+  int dev = 0, ncu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, BLOCK, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  int64_t blocks = static_cast<int64_t>(ncu) * per_cu;
+  if (blocks > c.ntiles) blocks = c.ntiles;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), lds, st, species_args<T>(c, sp),
                      grid_args(c), global_fields<T>(c, f), global_current<T>(c, f), t, c.wsp<int32_t>(c.ws.flags));
   return hipGetLastError();
 }
@@ -605,8 +639,9 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
   t.ntiles = c.ntiles;
   t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
   t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
+  t.queue = t.stray_count + 1;
   t.cross_cap = c.cross_cap;
-  hipError_t e = launch_fill_zero(t.stray_count, 1, 4, st);
+  hipError_t e = launch_fill_zero(t.stray_count, 9, 4, st);  // the straggler count and the 8 queues
   if (e != hipSuccess) return e;
   const int *L = c.p.tile;
   const int sl = c.p.slack;

@@ -36,7 +36,7 @@ struct Workspace {
   size_t sort_key = 0;    // int32[max_particles]
   size_t sort_rank = 0;   // int32[max_particles]
   size_t sort_src = 0;    // int32[max_particles]: the particle each sorted slot takes
-  size_t stray_count = 0; // int32: particles the tiled kernel left outside their LDS box
+  size_t stray_count = 0; // int32[16]: [0] particles the tiled kernel left outside their LDS box, [1..8] its tile queues
   size_t stray_list = 0;  // int32[max_particles]: their indices
   size_t stay_count = 0;    // int32[ntiles * levels]: per (tile, level) bucket, particles that stayed in the tile
   size_t arrive_count = 0;  // int32[ntiles * levels]: per bucket, the others
