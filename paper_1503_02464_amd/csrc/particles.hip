@@ -60,6 +60,23 @@ __device__ __forceinline__ void absorb_if_out(const SpeciesArgs<T> &s, int64_t p
   if (s.open && (cx < s.xlo || cx >= s.xhi)) s.w[p] = T(0);
 }
 
+// Deal each wavefront's particles to lanes by the bank residue of their
+// deposit window (the fused kernel, FP32 state in 3D).  There the deposit's
+// 54 FP64 LDS atomics per particle dominate; in 2D (21 atomics) the exchange
+// costs more than it saves, and the FP64 state is bound by its arithmetic.
+constexpr bool kDealLanes = true;
+
+// A value sent from this lane to lane to/4 of the wavefront.
+__device__ __forceinline__ int32_t lane_push(int to, int32_t v) { return __builtin_amdgcn_ds_permute(to, v); }
+__device__ __forceinline__ float lane_push(int to, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_push(int to, double v) {
+  const int lo = __builtin_amdgcn_ds_permute(to, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_permute(to, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_particle(const SpeciesArgs<T> &s, int64_t p, T o[3], T u[3]) {
 #pragma unroll
@@ -325,23 +342,78 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     // The next particle's data is loaded before the current one is processed,
-    // so its HBM latency hides behind the gather, push and deposit.
-    int64_t p = pbeg + threadIdx.x;
+    // so its HBM latency hides behind the gather, push and deposit.  The trip
+    // count is the same for every thread: lanes without a particle still take
+    // part in the wavefront's exchange below.
+    const int64_t trips = (pend - pbeg + BLOCK - 1) / BLOCK;
+    int64_t pn = pbeg + threadIdx.x;
     int32_t n_cell = 0;
     T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
-    if (p < pend) {
-      n_cell = s.cell[p];
-      n_w = s.w[p];
-      load_particle<T, D>(s, p, n_o, n_u);
+    if (pn < pend) {
+      n_cell = s.cell[pn];
+      n_w = s.w[pn];
+      load_particle<T, D>(s, pn, n_o, n_u);
     }
-    for (; p < pend; p += BLOCK) {
-      const int32_t p_cell = n_cell;
-      const T w = n_w;
+    for (int64_t trip = 0; trip < trips; ++trip, pn += BLOCK) {
+      int32_t p_cell = n_cell;
+      T w = n_w;
       T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
-      if (p + BLOCK < pend) {
-        n_cell = s.cell[p + BLOCK];
-        n_w = s.w[p + BLOCK];
-        load_particle<T, D>(s, p + BLOCK, n_o, n_u);
+      const bool have = pn < pend;
+      if (pn + BLOCK < pend) {
+        n_cell = s.cell[pn + BLOCK];
+        n_w = s.w[pn + BLOCK];
+        load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
+      }
+      int64_t p = pn;
+      if constexpr (kDealLanes && D == 3 && sizeof(T) == 4) {
+        // The LDS unit serves a wavefront's 8-byte atomics 16 lanes at a time
+        // and replays a group once per repeat of (element index mod 16)
+        // within it.  Every deposit atomic of a particle sits at a fixed
+        // offset from its window base, so that residue of the base decides.
+        // Sort the wavefront's particles by it and deal them round-robin over
+        // the four 16-lane groups: copies of one residue land in different
+        // groups as long as there are at most four of them.
+        int key = 16;  // lanes without a particle sort last
+        if (have) {
+          int c0[3];
+          unpack(p_cell, g, c0);
+          int idx = 0, stride = 1;
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            int l = c0[d] - T0[d];
+            if (l > g.n[d] / 2) l -= g.n[d];
+            if (l < -g.n[d] / 2) l += g.n[d];
+            const int b = l + (M == 2 ? (o[d] >= T(0.5) ? 0 : -1) : 0);
+            idx += stride * (b + geo.JLO);
+            stride *= d == 0 ? geo.JX : geo.JY;
+          }
+          key = idx & 15;
+        }
+        int before = 0, run = 0;
+        uint64_t mine = 0;
+#pragma unroll
+        for (int r = 0; r <= 16; ++r) {
+          const uint64_t m = __ballot(key == r);
+          if (key == r) {
+            mine = m;
+            before = run;
+          }
+          run += __popcll(m);
+        }
+        const int k = before + __popcll(mine & below);
+        const int to = ((k & 3) * 16 + (k >> 2)) * 4;
+        p_cell = lane_push(to, p_cell);
+        w = lane_push(to, w);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d < D) o[d] = lane_push(to, o[d]);
+          u[d] = lane_push(to, u[d]);
+        }
+        const int32_t got = lane_push(to, have ? static_cast<int32_t>(pn - pbeg) : int32_t(-1));
+        if (got < 0) continue;
+        p = pbeg + got;
+      } else {
+        if (!have) continue;
       }
       int c[3];
       unpack(p_cell, g, c);
