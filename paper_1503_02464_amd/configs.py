@@ -190,5 +190,5 @@ WORKLOADS = {"uniform-2d-64": uniform_2d_small, "laser-foil-2d": laser_foil_2d, 
 # Launch configuration of the fused step for the 3D benchmark workload, per
 # precision: cells per tile, guard slack, sort cadence.  The FP64 tile is
 # halved in z so fields + current + the wide-window list fit 160 KB of LDS.
-BENCH_LAUNCH = {"fp32": {"tile": (8, 8, 8), "slack": 1, "sort_every": 8},
-                "fp64": {"tile": (8, 8, 4), "slack": 1, "sort_every": 8}}
+BENCH_LAUNCH = {"fp32": {"tile": (8, 8, 8), "slack": 1, "sort_every": 12},
+                "fp64": {"tile": (8, 8, 4), "slack": 1, "sort_every": 12}}

@@ -99,6 +99,7 @@ class Simulation:
         p.tile = L._c3i(*tile)
         p.slack = slack
         p.sort_every = sort_every
+        self.sort_every = int(sort_every)
         p.max_particles = int(max_particles)
         p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64}[current_accum]
         p.open_x = 1 if open_x else 0

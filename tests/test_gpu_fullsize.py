@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size and launch configuration: the 3D3V
 thermal plasma, 256^3 cells, 8 ppc (134,217,728 particles), quadratic shape,
-FP32 state, 8x8x8 tiles, slack 1, sort every 8 steps, FP64 LDS current.
+FP32 state, 8x8x8 tiles, slack 1, sort every 12 steps, FP64 LDS current.
 
 The oracle cannot step the whole box in a test, so it checks what it can
 compute piecewise: sampled particles of a step that does not re-sort (the
