@@ -100,6 +100,7 @@ struct CountLds {
   uint32_t bits[kOrderWords];
   int32_t prefix[kOrderWords];
   int64_t seg[kMaxLevels + 1];
+  int64_t raw[kMaxLevels];
 };
 
 // One run (or chunk) b, by the whole workgroup.
@@ -113,6 +114,7 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
   uint32_t *bits = sh.bits;
   int32_t *prefix = sh.prefix;
   int64_t *seg = sh.seg;
+  int64_t *raw = sh.raw;
   const bool order = runs != nullptr && hints != nullptr && b < nruns && rg.words > 0;
   int64_t lo, hi;
   if (runs) {  // run b of the previous sort; the extra last workgroup takes any tail
@@ -127,13 +129,16 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
   if (lo >= hi) return;  // an empty run: its stayer counts are already zero
   if (order) {
     for (int i = threadIdx.x; i < levels * rg.words; i += kCountBlock) bits[i] = 0u;
-    // previous level segments, clamped to partition [lo, hi): the starts are
-    // loaded in parallel, then made monotonic
-    if (threadIdx.x < levels) seg[threadIdx.x] = threadIdx.x == 0 ? lo : hints[b * levels + threadIdx.x];
+    // previous level segments, clamped to partition [lo, hi): segment l
+    // starts at the largest of the first l + 1 hinted starts (the first is
+    // lo), at most hi
+    if (threadIdx.x < levels) raw[threadIdx.x] = threadIdx.x == 0 ? lo : hints[b * levels + threadIdx.x];
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int l = 1; l < levels; ++l) seg[l] = seg[l] < seg[l - 1] ? seg[l - 1] : (seg[l] > hi ? hi : seg[l]);
-      seg[levels] = hi;
+    if (threadIdx.x <= levels) {
+      int64_t v = lo;
+      if (threadIdx.x < levels)
+        for (int l = 0; l <= static_cast<int>(threadIdx.x); ++l) v = raw[l] > v ? raw[l] : v;
+      seg[threadIdx.x] = threadIdx.x < levels && v < hi ? v : hi;
     }
   } else {
     for (int i = threadIdx.x; i < kRankSlots; i += kCountBlock) counter[i] = 0;
@@ -168,8 +173,14 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
       }
       int level;
       if (order) {
-        int l0 = 0;  // previous level: the last segment starting at or before p
-        for (int l = 1; l < levels; ++l) l0 = seg[l] <= p ? l : l0;
+        // previous level: the last segment starting at or before p (the
+        // starts are non-decreasing and seg[0] = lo <= p)
+        int l0 = 0, l1 = levels - 1;
+        while (l0 < l1) {
+          const int mid = (l0 + l1 + 1) >> 1;
+          if (seg[mid] <= p) l0 = mid;
+          else l1 = mid - 1;
+        }
         level = l0;
         if (tile == b) {  // a stayer's nearest node lies in [T0, T0 + L] per dimension
           const int v = (nd[0] - T0[0]) + rg.nl[0] * ((nd[1] - T0[1]) + rg.nl[1] * (nd[2] - T0[2]));
