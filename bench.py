@@ -5,7 +5,7 @@ per cell (134,217,728 particles), Maxwellian momenta with spread 0.05 m_e c,
 quadratic shape, dx = 0.05 c/omega_p, dt = 0.7 of the Yee limit; synthetic,
 seeded inputs resident in HBM before timing starts.
 
-One step = the whole forward step: the tile sort (every 8th step, amortised),
+One step = the whole forward step: the tile sort (every 12th step, amortised),
 clearing J, the fused gather + Boris + Esirkepov deposit per tile, and the Yee
 update.  value = particle pushes per second over the timed steps.
 
@@ -15,8 +15,8 @@ Also printed, in the same JSON line:
   against the 8 TB/s HBM peak; traffic = HBM bytes per launch from the
   FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ (null once the
   kernel sources differ from the ones they were taken on);
-* cpu_baseline: the FP64 CPU oracle, one thread, one step of a 64^3 box of
-  the same workload;
+* cpu_baseline: the FP64 CPU oracle, one thread, whole steps of a 64^3 box
+  of the same workload (about 10 s);
 * fp64: the same step in FP64 (value and roofline);
 * adjoint: forward and backward time of the differentiable 2D rollout;
 * laser_foil: time per step of the two laser-on-foil boxes (FP32).

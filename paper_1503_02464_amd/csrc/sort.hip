@@ -11,8 +11,8 @@
 // levels and ranks with LDS counters and bitmaps (see k_sort_count); (2) an
 // exclusive scan of the bucket counts (multi-block) gives the bucket starts
 // and the tile starts; (3) every particle's slot is found, then every array
-// is copied into the second set in slot order.  Particles removed at an open face go to one last bucket behind
-// every tile.
+// is copied into the second set in slot order.  Particles removed at an open
+// face go to one last bucket behind every tile.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -90,7 +90,7 @@ struct RankGeom {
 //    nodes.  Stayers are then ranked inside their (tile, level) bucket by node,
 //    so a bucket holds its stayers in node order and a particle whose node and
 //    level did not change keeps its place: the permutation stays close to a
-//    shift, and the scatter's writes stay coalesced.  A particle that left
+//    shift, and the copy's reads stay mostly contiguous.  A particle that left
 //    the tile keeps its level and arrives after the stayers of its new bucket.
 constexpr int kMaxLevels = kMaxSortLevels;
 constexpr int32_t kDeferred = INT32_MIN;  // a stayer whose previous level was taken
@@ -480,7 +480,7 @@ void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_r
 }
 
 template <typename T, int D>
-void scatter(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
+void reorder(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
   int32_t *src = c.wsp<int32_t>(c.ws.sort_src);
   hipLaunchKernelGGL(k_sort_slots, dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
@@ -562,9 +562,9 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
   if (sp.np > 0) {
     const bool f64 = c.p.precision == PIC_FP64;
     if (f64)
-      (c.p.dims == 3) ? scatter<double, 3>(c, sp, start, s) : scatter<double, 2>(c, sp, start, s);
+      (c.p.dims == 3) ? reorder<double, 3>(c, sp, start, s) : reorder<double, 2>(c, sp, start, s);
     else
-      (c.p.dims == 3) ? scatter<float, 3>(c, sp, start, s) : scatter<float, 2>(c, sp, start, s);
+      (c.p.dims == 3) ? reorder<float, 3>(c, sp, start, s) : reorder<float, 2>(c, sp, start, s);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
