@@ -1,0 +1,117 @@
+"""Paths of the fused kernel that the uniform workloads rarely take, against
+the FP64 oracle: particles that drift out of their tile's slack between
+sorts (the HBM straggler path), more window-changing particles in one tile
+than its LDS list holds (deposited in place), and more non-empty tiles than
+resident workgroups (the per-XCD tile queues).  FP64 to 1e-12; FP32 one step
+from an FP32-representable state (gpu_helpers.TOL)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_helpers import compare_fields, compare_species, grid, make_sim, unique_weights
+from paper_1503_02464_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def drifting(g, prec, ppc, u_mean, seed):
+    sp = inputs.uniform_plasma(g.n, g.dims, ppc, 0.05, 1.0, seed, u_mean=u_mean)
+    sp = inputs.shuffle(sp, seed + 1)
+    sp = unique_weights(sp, seed + 2, scale=float(np.prod(g.dx[:g.dims])) / ppc)
+    f = inputs.random_fields(g.ncells, 0.1, seed + 3)
+    if prec == "fp32":
+        sp, f = inputs.round_f32(sp), inputs.round_fields_f32(f)
+    return sp, f
+
+
+def gpu_state(s, h):
+    sp = s.get_species(h)
+    f = s.get_fields()
+    return sp, f
+
+
+@pytest.mark.parametrize("prec,dims", [(p, d) for p in ("fp64", "fp32") for d in (2, 3)])
+def test_stragglers(prec, dims):
+    """Slack 0 and no re-sort: after the first step every particle that left its
+    tile is a straggler.  FP64: three steps against three oracle steps.  FP32:
+    the third step against one oracle step from the GPU's second state."""
+    g = grid(dims, (32, 16) if dims == 2 else (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    sp, f = drifting(g, prec, 2, (2.0, -1.0, 0.5), seed=600 + dims)
+    tile = (8, 4, 1) if dims == 2 else (8, 4, 4)
+    s = make_sim(g, prec, tile, slack=0, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    for n in range(3):
+        if prec == "fp32" and n == 2:
+            ref_sp, ref_f = gpu_state(s, h)
+            ref_sp["q"], ref_sp["m"] = sp["q"], sp["m"]
+            ref_f["J"] = np.zeros_like(ref_f["J"])
+        s.step(1)
+        if prec == "fp64" or n == 2:
+            assert O.step(g, ref_f, [ref_sp]) == 0
+    s.check()
+    assert s.straggler_count() > sp["w"].shape[0] // 20, s.straggler_count()
+    compare_species(g, prec, s.get_species(h), ref_sp, "stragglers")
+    compare_fields(prec, s.get_fields(), ref_f, what="stragglers")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_list_overflow(prec):
+    """Several thousand particles in one tile all cross a half-cell in x in the
+    same step (so each changes its deposit window): more than the LDS list of
+    the production tile shape holds, so the rest deposit in place."""
+    g = grid(3, (16, 16, 16), dx=0.05, cfl=0.7, order=2)
+    r = inputs.rng(620)
+    npart = 6000
+    sp = {"q": -1.0, "m": 1.0, "cell": np.zeros((3, npart), np.int32), "off": np.zeros((3, npart)),
+          "u": np.zeros((3, npart)), "w": np.ones(npart)}
+    sp["cell"][0] = r.integers(0, 8, npart)
+    sp["cell"][1] = r.integers(0, 8, npart)
+    sp["cell"][2] = r.integers(0, 4 if prec == "fp64" else 8, npart)  # one tile of 8x8x4 (FP64) or 8^3 (FP32)
+    sp["off"][0] = 0.5 - r.uniform(0.001, 0.05, npart)  # just below the half-cell, heading +x
+    sp["off"][1] = r.random(npart)
+    sp["off"][2] = r.random(npart)
+    sp["u"][0] = r.uniform(0.6, 1.5, npart)
+    sp["u"][1:] = r.normal(0, 0.1, (2, npart))
+    sp = unique_weights(sp, 621, scale=1e-3)
+    f = inputs.random_fields(g.ncells, 0.05, 622)
+    if prec == "fp32":
+        sp, f = inputs.round_f32(sp), inputs.round_fields_f32(f)
+    tile = (8, 8, 8) if prec == "fp32" else (8, 8, 4)
+    s = make_sim(g, prec, tile, slack=1, sort_every=4, max_particles=npart)
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    crossed = np.sum((ref_sp["off"][0] >= 0.5) | (ref_sp["cell"][0] != sp["cell"][0]))
+    assert crossed > 4 * 512, crossed
+    compare_species(g, prec, s.get_species(h), ref_sp, "wide overflow")
+    compare_fields(prec, s.get_fields(), ref_f, what="wide overflow")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_more_tiles_than_workgroups(prec):
+    """More non-empty tiles than the device runs workgroups of the production
+    tile shape at once, so workgroups take further tiles from the per-XCD
+    queues (and from other XCDs' queues at the end); two steps, each sorting."""
+    g = grid(3, (64, 64, 40), dx=0.05, cfl=0.7, order=2)
+    sp, f = drifting(g, prec, 2 if prec == "fp64" else 4, (0.0, 0.0, 0.0), seed=640)
+    tile = (8, 8, 8) if prec == "fp32" else (8, 8, 4)
+    s = make_sim(g, prec, tile, slack=1, sort_every=1, max_particles=sp["w"].shape[0])
+    assert s.ntiles > 256
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    nsteps = 2 if prec == "fp64" else 1
+    for _ in range(nsteps):
+        s.step(1)
+        assert O.step(g, ref_f, [ref_sp]) == 0
+    s.check()
+    compare_species(g, prec, s.get_species(h), ref_sp, "queues")
+    compare_fields(prec, s.get_fields(), ref_f, what="queues")
+    s.close()
