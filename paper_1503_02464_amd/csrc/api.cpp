@@ -201,8 +201,9 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
       c->rf[d] = c->rj[d] = 1;
     }
   }
+  c->jxy = pic::current_plane_stride(c->rj[0], c->rj[1], p->dims);
   const size_t boxes = 6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] * c->elem +
-                       3 * static_cast<size_t>(c->rj[0]) * c->rj[1] * c->rj[2] * jelem;
+                       3 * static_cast<size_t>(c->jxy) * c->rj[2] * jelem;
   if (boxes + pic::cross_list_bytes(c->elem, 0) > pic::kLdsLimit) {
     delete c;
     return PIC_EINVAL;

@@ -187,6 +187,7 @@ struct TileArgs {
   int ntile[3];   // tiles per dimension
   int slack;
   int rf[3], rj[3];        // LDS field / current box sizes
+  int jxy;                 // plane stride of the current box (padded in 3D)
   int gf_lo[3], gj_lo[3];  // box origins below the tile origin
   int remap;               // 1: spread consecutive tiles over XCDs in blocks
   const int32_t *live;     // non-empty tiles in order, count at [ntiles] (null: every tile)
@@ -205,17 +206,18 @@ struct FixedGeom {
   static constexpr int FX = LX + 1 + M + 2 * SL, FY = LY + 1 + M + 2 * SL, FZ = D == 3 ? LZ + 1 + M + 2 * SL : 1;
   static constexpr int JX = LX + 2 * M + 1 + 2 * SL, JY = LY + 2 * M + 1 + 2 * SL,
                        JZ = D == 3 ? LZ + 2 * M + 1 + 2 * SL : 1;
-  static constexpr int FVOL = FX * FY * FZ, JVOL = JX * JY * JZ;
+  static constexpr int JXY = current_plane_stride(JX, JY, D);
+  static constexpr int FVOL = FX * FY * FZ, JVOL = JXY * JZ;
   __device__ explicit FixedGeom(const TileArgs &) {}
 };
 
 // Tile geometry from the launch arguments (any tile shape).
 struct RuntimeGeom {
-  int L0, L1, L2, S, FLO, JLO, FX, FY, FZ, JX, JY, JZ, FVOL, JVOL;
+  int L0, L1, L2, S, FLO, JLO, FX, FY, FZ, JX, JY, JZ, JXY, FVOL, JVOL;
   __device__ explicit RuntimeGeom(const TileArgs &t)
       : L0(t.L[0]), L1(t.L[1]), L2(t.L[2]), S(t.slack), FLO(t.gf_lo[0]), JLO(t.gj_lo[0]), FX(t.rf[0]), FY(t.rf[1]),
-        FZ(t.rf[2]), JX(t.rj[0]), JY(t.rj[1]), JZ(t.rj[2]), FVOL(t.rf[0] * t.rf[1] * t.rf[2]),
-        JVOL(t.rj[0] * t.rj[1] * t.rj[2]) {}
+        FZ(t.rf[2]), JX(t.rj[0]), JY(t.rj[1]), JZ(t.rj[2]), JXY(t.jxy), FVOL(t.rf[0] * t.rf[1] * t.rf[2]),
+        JVOL(t.jxy * t.rj[2]) {}
 };
 
 template <typename T, class G, int D>
@@ -232,7 +234,7 @@ struct FieldBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
 template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
 struct CurrentBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
   using G = FixedGeom<D, M, LX, LY, LZ, SL>;
-  using type = LdsBox<T, G::JX, G::JX * G::JY, G::JVOL, G::JLO, G::JLO, D == 3 ? G::JLO : 0>;
+  using type = LdsBox<T, G::JX, G::JXY, G::JVOL, G::JLO, G::JLO, D == 3 ? G::JLO : 0>;
   __device__ static type make(T *base, const G &) { return type{base}; }
 };
 template <typename T, int DD>
@@ -246,7 +248,7 @@ template <typename T, int DD>
 struct CurrentBox<T, RuntimeGeom, DD> {
   using type = LdsCurrent<T>;
   __device__ static type make(T *base, const RuntimeGeom &g) {
-    return type{base, g.JX, g.JX * g.JY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0};
+    return type{base, g.JX, g.JXY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0};
   }
 };
 
@@ -377,15 +379,15 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         if (have) {
           int c0[3];
           unpack(p_cell, g, c0);
-          int idx = 0, stride = 1;
+          const int stride[3] = {1, geo.JX, geo.JXY};
+          int idx = 0;
 #pragma unroll
           for (int d = 0; d < D; ++d) {
             int l = c0[d] - T0[d];
             if (l > g.n[d] / 2) l -= g.n[d];
             if (l < -g.n[d] / 2) l += g.n[d];
             const int b = l + (M == 2 ? (o[d] >= T(0.5) ? 0 : -1) : 0);
-            idx += stride * (b + geo.JLO);
-            stride *= d == 0 ? geo.JX : geo.JY;
+            idx += stride[d] * (b + geo.JLO);
           }
           key = idx & 15;
         }
@@ -514,10 +516,11 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     __syncthreads();
 
     // add the current box into HBM (skipping cells nothing touched)
-    for (int idx = threadIdx.x; idx < geo.JVOL; idx += BLOCK) {
-      const int li = idx % geo.JX;
-      const int lj2 = (idx / geo.JX) % geo.JY;
-      const int lk = idx / (geo.JX * geo.JY);
+    for (int cell = threadIdx.x; cell < geo.JX * geo.JY * geo.JZ; cell += BLOCK) {
+      const int li = cell % geo.JX;
+      const int lj2 = (cell / geo.JX) % geo.JY;
+      const int lk = cell / (geo.JX * geo.JY);
+      const int idx = li + geo.JX * lj2 + geo.JXY * lk;  // the plane stride may be padded
       const int gi = wrap_full(T0[0] - geo.JLO + li, g.n[0]);
       const int gjj = wrap_full(T0[1] - geo.JLO + lj2, g.n[1]);
       const int gk = D == 3 ? wrap_full(T0[2] - geo.JLO + lk, g.n[2]) : 0;
@@ -706,6 +709,7 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
     t.gj_lo[d] = c.gj_lo[d];
   }
   t.slack = c.p.slack;
+  t.jxy = c.jxy;
   t.remap = c.ntiles >= 64 ? 1 : 0;
   t.live = live_tiles(c, sp);
   t.ntiles = c.ntiles;

@@ -28,6 +28,14 @@ constexpr size_t kLdsLimit = 160 * 1024;
 // factor, packed cell; plus its length.
 inline size_t cross_list_bytes(size_t elem, int cap) { return static_cast<size_t>(cap) * (8 * elem + 4) + 16; }
 
+// Plane stride of the fused kernel's LDS current box (elements).  In 3D it
+// is padded to the next value that is 7 mod 16: with the 15-element rows of
+// an 8^3 tile's box, the window bases' element indices then fall evenly into
+// the 16 residue classes that decide the LDS unit's 8-byte atomic replays.
+__host__ __device__ constexpr int current_plane_stride(int jx, int jy, int dims) {
+  return dims == 3 ? jx * jy + ((7 - jx * jy) % 16 + 16) % 16 : jx * jy;
+}
+
 // Byte offsets of the workspace regions (each 256-byte aligned).
 struct Workspace {
   size_t flags = 0;       // int32[64]: sticky device flags
@@ -70,6 +78,7 @@ struct pic_ctx {
   // LDS tile geometry of the fused kernel: field and current regions per
   // dimension, starting gf_lo / gj_lo cells below the tile origin.
   int32_t rf[3] = {1, 1, 1}, rj[3] = {1, 1, 1};
+  int32_t jxy = 1;  // plane stride of the current box (current_plane_stride)
   int32_t gf_lo[3] = {0, 0, 0}, gj_lo[3] = {0, 0, 0};
   size_t lds_bytes = 0;
   bool acc64 = true;  // LDS current box accumulated in double

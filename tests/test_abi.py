@@ -61,9 +61,10 @@ def test_valid_init_and_queries(lib):
     bits = (ctypes.c_int32 * 3)()
     lib.pic_cell_bits(ctx, bits)
     assert tuple(bits) == (4, 4, 4)
-    # LDS: fields (8+1+2+2)^3 * 6 in FP32 + current (8+2+3+2)^3 * 3 accumulated in FP64
+    # LDS: fields (8+1+2+2)^3 * 6 in FP32 + current (8+2+3+2)^3 * 3 accumulated in FP64, its
+    # planes padded from 15 * 15 = 225 to 231 elements (the next value that is 7 mod 16)
     # + a list of 512 wide-window particles (8 FP32 values + one int each) and its length
-    assert lib.pic_tile_lds_bytes(ctx) == 13 ** 3 * 6 * 4 + 15 ** 3 * 3 * 8 + 512 * 36 + 16
+    assert lib.pic_tile_lds_bytes(ctx) == 13 ** 3 * 6 * 4 + 231 * 15 * 3 * 8 + 512 * 36 + 16
     assert lib.pic_step_count(ctx) == 0
     lib.pic_destroy(ctx)
 
