@@ -61,9 +61,9 @@ __device__ __forceinline__ void absorb_if_out(const SpeciesArgs<T> &s, int64_t p
 }
 
 // Deal each wavefront's particles to lanes by the bank residue of their
-// deposit window (the fused kernel, FP32 state in 3D).  There the deposit's
-// 54 FP64 LDS atomics per particle dominate; in 2D (21 atomics) the exchange
-// costs more than it saves, and the FP64 state is bound by its arithmetic.
+// deposit window (the fused kernel in 3D, where the deposit's 54 FP64 LDS
+// atomics per particle weigh most; in 2D, with 21, the exchange costs more
+// than it saves).
 constexpr bool kDealLanes = true;
 
 // A value sent from this lane to lane to/4 of the wavefront.
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
       }
       int64_t p = pn;
-      if constexpr (kDealLanes && D == 3 && sizeof(T) == 4) {
+      if constexpr (kDealLanes && D == 3) {
         // The LDS unit serves a wavefront's 8-byte atomics 16 lanes at a time
         // and replays a group once per repeat of (element index mod 16)
         // within it.  Every deposit atomic of a particle sits at a fixed
