@@ -68,33 +68,42 @@ struct PhaseTimer {
   PhaseTimer(pic_ctx *c_, hipStream_t s_, int ph) : c(c_), s(s_), phase(ph) {
     if (!c->timing) return;
     a = take();
-    hipEventRecord(a, s);
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+      c->spare.push_back(a);
+      a = nullptr;
+    }
   }
+  // A recycled event, or a new one (null if it cannot be created: that
+  // phase then goes untimed).
   hipEvent_t take() {
-    hipEvent_t e;
+    hipEvent_t e = nullptr;
     if (!c->spare.empty()) {
       e = c->spare.back();
       c->spare.pop_back();
-    } else {
-      hipEventCreate(&e);
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
     }
     return e;
   }
   ~PhaseTimer() {
     if (!c->timing || !a) return;
     hipEvent_t b = take();
-    hipEventRecord(b, s);
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+      c->spare.push_back(a);
+      if (b) c->spare.push_back(b);
+      return;
+    }
     c->events.push_back({phase, a, b});
   }
 };
 
 void collect_timing(pic_ctx *c) {
   for (auto &ev : c->events) {
-    hipEventSynchronize(ev.b);
     float ms = 0.f;
-    hipEventElapsedTime(&ms, ev.a, ev.b);
-    c->ms[ev.phase] += ms;
-    c->launches[ev.phase] += 1;
+    if (hipEventSynchronize(ev.b) == hipSuccess && hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+      c->ms[ev.phase] += ms;
+      c->launches[ev.phase] += 1;
+    }
     c->spare.push_back(ev.a);
     c->spare.push_back(ev.b);
   }

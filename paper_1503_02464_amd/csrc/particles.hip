@@ -661,12 +661,11 @@ hipError_t launch_tiled_acc(const pic_ctx &c, const pic_species &sp, const pic_f
                             hipStream_t st) {
   const auto kern = k_push_deposit_tiled<T, D, M, G, BLOCK, TJ>;
   const size_t lds = c.lds_bytes;
-  static size_t lds_set = 0;  // largest dynamic LDS size granted to this instantiation
-  if (lds > 65536 && lds > lds_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  // granted on every launch (idempotent, and valid for whichever device is current)
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
-    lds_set = lds;
   }
   // persistent workgroups: as many as the device holds at once, at most one per tile
   int dev = 0, ncu = 0, per_cu = 0;
