@@ -357,8 +357,8 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       load_particle<T, D>(s, pn, n_o, n_u);
     }
     for (int64_t trip = 0; trip < trips; ++trip, pn += BLOCK) {
-      int32_t p_cell = n_cell;
-      T w = n_w;
+      const int32_t p_cell = n_cell;
+      const T w = n_w;
       T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
       const bool have = pn < pend;
       if (pn + BLOCK < pend) {
@@ -366,27 +366,67 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         n_w = s.w[pn + BLOCK];
         load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
       }
-      int64_t p = pn;
+      const int64_t p = pn;
+      int c[3] = {0, 0, 0};
+      // cell relative to the tile origin, unwrapped across the periodic seam
+      int lc[3] = {0, 0, 0};
+      bool inside = true;
+      if (have) {
+        unpack(p_cell, g, c);
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          int l = c[d] - T0[d];
+          if (l > g.n[d] / 2) l -= g.n[d];
+          if (l < -g.n[d] / 2) l += g.n[d];
+          lc[d] = l;
+          const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
+          inside = inside && (l >= -geo.S) && (l < L + geo.S);
+        }
+      }
+      const bool stray = have && !inside;
+      const uint64_t out = __ballot(stray);
+      if (out) {  // list the particles outside the box for the HBM path
+        const int leader = __ffsll(static_cast<unsigned long long>(out)) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(t.stray_count, __popcll(out));
+        base = __shfl(base, leader);
+        if (stray) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
+      }
+      // removed at an open face: skipped until the next sort drops it
+      const bool live = have && inside && !(s.open && w == T(0));
+      T on[3] = {T(0), T(0), T(0)};
+      int dc[3] = {0, 0, 0};
+      T jz = T(0);
+      bool wide = false, fast = false;
+      if (live) {
+        T eb[6];
+        gather_eb<T, D, M>(lf, lc, o, eb);
+        boris<T>(u, eb, s.h);
+        const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
+        if (!ok) atomicOr(&flags[0], kFlagCross);
+        jz = D == 2 ? s.jz * u[2] * ig : T(0);
+        wide = ok && crosses<T, D, M>(o, dc, on);
+        fast = ok && !wide;
+      }
       if constexpr (kDealLanes && D == 3) {
         // The LDS unit serves a wavefront's 8-byte atomics 16 lanes at a time
         // and replays a group once per repeat of (element index mod 16)
         // within it.  Every deposit atomic of a particle sits at a fixed
         // offset from its window base, so that residue of the base decides.
-        // Sort the wavefront's particles by it and deal them round-robin over
-        // the four 16-lane groups: copies of one residue land in different
-        // groups as long as there are at most four of them.
-        int key = 16;  // lanes without a particle sort last
-        if (have) {
-          int c0[3];
-          unpack(p_cell, g, c0);
+        // The wavefront sorts its fast deposits by it and deals them
+        // round-robin over its four 16-lane groups: copies of one residue
+        // land in different groups as long as there are at most four.  Only
+        // the deposit's inputs move; gather, push and stores stay in the
+        // particles' own lanes, where neighbouring lanes hold neighbouring
+        // nodes and the field reads spread over the banks.
+        int key = 16;  // lanes without a fast deposit sort last
+        if (fast) {
           const int stride[3] = {1, geo.JX, geo.JXY};
           int idx = 0;
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            int l = c0[d] - T0[d];
-            if (l > g.n[d] / 2) l -= g.n[d];
-            if (l < -g.n[d] / 2) l += g.n[d];
-            const int b = l + (M == 2 ? (o[d] >= T(0.5) ? 0 : -1) : 0);
+            const int b = lc[d] + (M == 2 ? (o[d] >= T(0.5) ? 0 : -1) : 0);
             idx += stride[d] * (b + geo.JLO);
           }
           key = idx & 15;
@@ -404,58 +444,29 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         }
         const int k = before + __popcll(mine & below);
         const int to = ((k & 3) * 16 + (k >> 2)) * 4;
-        p_cell = lane_push(to, p_cell);
-        w = lane_push(to, w);
+        T so[3], sn[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          if (d < D) o[d] = lane_push(to, o[d]);
-          u[d] = lane_push(to, u[d]);
+          so[d] = lane_push(to, o[d]);
+          sn[d] = lane_push(to, on[d]);
         }
-        const int32_t got = lane_push(to, have ? static_cast<int32_t>(pn - pbeg) : int32_t(-1));
-        if (got < 0) continue;
-        p = pbeg + got;
+        const int32_t sk = lane_push(to, fast ? pack_local(lc, dc) : int32_t(0));
+        const T sw = lane_push(to, w);
+        if (lane_push(to, fast ? int32_t(1) : int32_t(0))) {
+          int slc[3], sdc[3];
+          unpack_local(sk, slc, sdc);
+          Esirk<T, M> e;
+          esirkepov_factors<T, D, M>(so, sdc, sn, e);
+          const T jc[3] = {sw * s.jc[0], sw * s.jc[1], sw * s.jc[2]};
+          esirkepov_accumulate<T, D, M, true>(lj, slc, e, jc, T(0));
+        }
       } else {
-        if (!have) continue;
-      }
-      int c[3];
-      unpack(p_cell, g, c);
-      // cell relative to the tile origin, unwrapped across the periodic seam
-      int lc[3] = {0, 0, 0};
-      bool inside = true;
-#pragma unroll
-      for (int d = 0; d < D; ++d) {
-        int l = c[d] - T0[d];
-        if (l > g.n[d] / 2) l -= g.n[d];
-        if (l < -g.n[d] / 2) l += g.n[d];
-        lc[d] = l;
-        const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
-        inside = inside && (l >= -geo.S) && (l < L + geo.S);
-      }
-      const uint64_t out = __ballot(!inside);
-      if (out) {  // list the particles outside the box for the HBM path
-        const int leader = __ffsll(static_cast<unsigned long long>(out)) - 1;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(t.stray_count, __popcll(out));
-        base = __shfl(base, leader);
-        if (!inside) t.stray_list[base + __popcll(out & below)] = static_cast<int32_t>(p);
-      }
-      if (!inside) continue;
-      if (s.open && w == T(0)) continue;  // removed at an open face, until the next sort drops it
-      T eb[6];
-      gather_eb<T, D, M>(lf, lc, o, eb);
-      boris<T>(u, eb, s.h);
-      const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-      T on[3] = {T(0), T(0), T(0)};
-      int dc[3] = {0, 0, 0};
-      const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
-      if (!ok) atomicOr(&flags[0], kFlagCross);
-      const T jz = D == 2 ? s.jz * u[2] * ig : T(0);
-      const bool wide = ok && crosses<T, D, M>(o, dc, on);
-      if (ok && !wide) {
-        Esirk<T, M> e;
-        esirkepov_factors<T, D, M>(o, dc, on, e);
-        const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-        esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
+        if (fast) {
+          Esirk<T, M> e;
+          esirkepov_factors<T, D, M>(o, dc, on, e);
+          const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+          esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
+        }
       }
       // one LDS atomic per wavefront reserves list slots for the wide ones
       const uint64_t wm = __ballot(wide);
@@ -483,16 +494,18 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           }
         }
       }
+      if (live) {
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-        s.off[d][p] = on[d];
+        for (int d = 0; d < D; ++d) {
+          c[d] = wrap_near(c[d] + dc[d], g.n[d]);
+          s.off[d][p] = on[d];
+        }
+        s.cell[p] = pack(c, g);
+        s.u[0][p] = u[0];
+        s.u[1][p] = u[1];
+        s.u[2][p] = u[2];
+        absorb_if_out(s, p, c[0]);
       }
-      s.cell[p] = pack(c, g);
-      s.u[0][p] = u[0];
-      s.u[1][p] = u[1];
-      s.u[2][p] = u[2];
-      absorb_if_out(s, p, c[0]);
     }
     __syncthreads();
 
