@@ -96,7 +96,8 @@ typedef struct {
     int32_t slack;         /* guard cells beyond the shape's reach in the LDS tile (0..4):
                               a particle may drift this far out of its tile between sorts
                               and still take the on-chip path */
-    int32_t sort_every;    /* pic_step re-sorts every this many steps (>= 1) */
+    int32_t sort_every;    /* pic_step re-sorts every this many steps (>= 1); 0: only species whose
+                              sorted flag is 0 (a fixed particle order after the first sort) */
     int64_t max_particles; /* the largest np of any species used with this context */
     int32_t current_accum; /* PIC_ACC_AUTO, PIC_ACC_FP32 (FP32 state only) or PIC_ACC_FP64 */
     /* Open x faces (the paper gives no boundary details, Sec. 2; this is the
@@ -222,7 +223,7 @@ pic_status pic_laser_current(pic_ctx *ctx, pic_fields *f, double t, void *stream
 pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
 
 /* nsteps whole steps for nspecies species: sort when needed (unsorted species,
- * or every sort_every steps), clear J, fused gather + push + deposit per tile
+ * or every sort_every steps when sort_every > 0), clear J, fused gather + push + deposit per tile
  * with fields and current staged on chip (and, with open_x, removal of the
  * particles that left), the laser sheet if one is registered, then the Yee
  * update. */

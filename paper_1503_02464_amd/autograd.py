@@ -2,9 +2,12 @@
 
 The loss is the total field energy U_E + U_B after K steps (FP64, from the
 library's diagnostics); the parameters are a per-cell source added to E_y at
-step 0 and the initial momenta u^{-1/2} of one species.  Forward runs K steps
-with the unfused pair (gather + push, deposit) and the Yee update, so the
-particle order never changes, and keeps a checkpoint every N steps.  Backward
+step 0 and the initial momenta u^{-1/2} of one species.  The species is sorted
+by tile once, when the rollout is built (the permutation is recorded, and
+parameters and gradients are mapped through it); forward then runs K fused
+steps (pic_step with sort_every = 0, so the particle order never changes;
+particles that drift out of their tile take the library's straggler path)
+and keeps a checkpoint every N steps.  Backward
 replays each segment from its checkpoint, keeping the state before every
 step, and walks it back with the library's hand-written adjoint
 (pic_energy_adjoint once, then per step pic_yee_adjoint and
@@ -51,16 +54,27 @@ class Rollout:
 
     def __init__(self, dims, n, dx, dt, order, precision, species: dict, steps: int, checkpoint_every: int,
                  device="cuda"):
-        # the rollout never sorts (particle order must match between forward and
-        # backward), so the tile shape only has to be valid
-        tile = tuple(next(t for t in (8, 4, 2, 1) if n[d] % t == 0) if d < dims else 1 for d in range(3))
-        self.sim = Simulation(dims, n, dx, dt, order, precision, tile=tile, slack=0, sort_every=1 << 30,
+        # the fused kernel's tile shapes (16x16 in 2D, 8x8x8 / 8x8x4 in 3D) where they divide the box
+        want = (16, 16, 1) if dims == 2 else ((8, 8, 8) if precision == "fp32" else (8, 8, 4))
+        tile = tuple(next(t for t in (want[d], 8, 4, 2, 1) if n[d] % t == 0) if d < dims else 1 for d in range(3))
+        self.sim = Simulation(dims, n, dx, dt, order, precision, tile=tile, slack=1, sort_every=0,
                               max_particles=species["w"].shape[0], device=device)
         self.steps = int(steps)
         self.every = int(checkpoint_every)
-        self.h = self.sim.add_species(species)
+        npart = int(species["w"].shape[0])
+        assert precision == "fp64" or npart < (1 << 24), "particle indices must be exact in the weight array"
+        # sort once with each particle's index + 1 in place of its weight: the
+        # sorted weights are then the permutation
+        tagged = dict(species)
+        tagged["w"] = np.arange(1, npart + 1, dtype=np.float64)
+        self.h = self.sim.add_species(tagged)
+        self.sim.sort(self.h)
         cur = self.h.current()
         self.npart = self.h.np
+        assert self.npart == npart
+        self.perm = (cur["w"][:npart].double().round().long() - 1)  # sorted slot -> original index
+        w0 = torch.as_tensor(np.asarray(species["w"], np.float64), device=self.sim.device)
+        cur["w"][:npart].copy_(w0[self.perm].to(self.sim.dtype))
         self.cell0 = cur["cell"][:self.npart].clone()
         self.off0 = [t[:self.npart].clone() for t in cur["off"]]
         self.w = cur["w"][:self.npart].clone()
@@ -88,11 +102,7 @@ class Rollout:
                 [t.clone() for t in self.sim.fields["E"]], [t.clone() for t in self.sim.fields["B"]])
 
     def _step(self):
-        s = self.sim
-        s.zero_current()
-        s.gather_push(self.h)
-        s.deposit(self.h)
-        s.yee_step()
+        self.sim.step(1, [self.h])
 
     def _energy(self) -> float:
         d = self.sim.diagnostics([self.h])
@@ -104,7 +114,7 @@ class Rollout:
         zeros = [torch.zeros(s.ncells, dtype=self.dtype, device=s.device) for _ in range(3)]
         E = [zeros[0], ey_src.detach().to(self.dtype).contiguous(), zeros[2]]
         B = [torch.zeros_like(zeros[0]) for _ in range(3)]
-        u = [u0[d].detach().to(self.dtype).contiguous() for d in range(3)]
+        u = [u0[d].detach()[self.perm].to(self.dtype).contiguous() for d in range(3)]
         self._set_state(self.cell0, self.off0, u, E, B)
         self.checkpoints = []
         for k in range(self.steps):
@@ -146,7 +156,9 @@ class Rollout:
                 s._call(lib.pic_particle_adjoint(s.ctx, ctypes.byref(spn), ctypes.byref(fn), ctypes.byref(lam_f),
                                                  ctypes.byref(lsp), st), "pic_particle_adjoint")
         s.check()
-        return lam["E"][1].clone(), torch.stack(lu)
+        gu = torch.empty((3, self.npart), dtype=dt, device=dev)
+        gu[:, self.perm] = torch.stack(lu)  # back to the caller's particle order
+        return lam["E"][1].clone(), gu
 
 
 class _RolloutFn(torch.autograd.Function):

@@ -150,7 +150,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   if (p->shape_order != 1 && p->shape_order != 2) return PIC_EINVAL;
   if (p->precision != PIC_FP32 && p->precision != PIC_FP64) return PIC_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t(1) << 31) - 1) return PIC_EINVAL;
-  if (p->sort_every < 1 || p->slack < 0 || p->slack > 4) return PIC_EINVAL;
+  if (p->sort_every < 0 || p->slack < 0 || p->slack > 4) return PIC_EINVAL;
   if (p->current_accum != PIC_ACC_AUTO && p->current_accum != PIC_ACC_FP32 && p->current_accum != PIC_ACC_FP64)
     return PIC_EINVAL;
   if (p->precision == PIC_FP64 && p->current_accum == PIC_ACC_FP32) return PIC_EINVAL;
@@ -398,7 +398,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   for (int it = 0; it < nsteps; ++it) {
-    const bool cadence = (c->step % c->p.sort_every) == 0;
+    const bool cadence = c->p.sort_every > 0 && (c->step % c->p.sort_every) == 0;
     for (int i = 0; i < nspecies; ++i) {
       if (sp[i].np > 0 && (cadence || !sp[i].sorted)) {
         PhaseTimer t(c, s, pic::kPhaseSort);

@@ -69,6 +69,12 @@ def test_valid_init_and_queries(lib):
     lib.pic_destroy(ctx)
 
 
+def test_sort_every_zero_is_valid(lib):
+    st, ctx = init(lib, params(sort_every=0))  # sort only species whose sorted flag is 0
+    assert st == L.PIC_OK
+    lib.pic_destroy(ctx)
+
+
 @pytest.mark.parametrize("cfl,want", [(0.999, L.PIC_OK), (1.0, L.PIC_ECFL), (1.2, L.PIC_ECFL)])
 def test_cfl_limit(lib, cfl, want):
     st, ctx = init(lib, params(cfl=cfl))
@@ -80,7 +86,7 @@ def test_cfl_limit(lib, cfl, want):
 @pytest.mark.parametrize("kw", [
     dict(dims=4), dict(order=3), dict(prec=7), dict(tile=(5, 8, 8)), dict(tile=(8, 8, 0)),
     dict(n=(16, 16, 2)), dict(dims=2, n=(16, 16, 4), tile=(8, 8, 1)), dict(dims=2, n=(16, 16, 1), tile=(8, 8, 2)),
-    dict(sort_every=0), dict(slack=5), dict(maxp=-1), dict(dx=(0.05, 0.0, 0.05)),
+    dict(sort_every=-1), dict(slack=5), dict(maxp=-1), dict(dx=(0.05, 0.0, 0.05)),
     dict(n=(64, 64, 64), tile=(32, 8, 8)),  # local cells must fit the packed 6-bit range
     dict(prec=L.PIC_FP64, tile=(16, 16, 16), n=(32, 32, 32)),  # LDS tile beyond 160 KB
     dict(acc=3), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32),
