@@ -257,7 +257,11 @@ pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies
  * rollout must not re-sort between the two) and the fields E^n, B^n: reads
  * lam.J and lsp (dL/dx^{n+1}, dL/du^{n+1/2}), replaces lsp by dL/dx^n,
  * dL/du^{n-1/2}, and adds the transpose of the gather to lam.E and lam.B.
- * Call it after pic_yee_adjoint of the same step, once per species.
+ * Call it after pic_yee_adjoint of the same step, once per species.  When
+ * state->tile_start is set (the tile ranges of the last pic_sort of these
+ * particles, in this order), it runs per tile with E, B and lam.J staged on
+ * chip, provided the tile's boxes fit in LDS; particles further than the
+ * slack from their tile, and every particle otherwise, take the HBM path.
  *
  * The adjoint covers periodic boxes only: all three return PIC_EINVAL when
  * open_x is set. */

@@ -152,6 +152,7 @@ class Rollout:
             for cell, off, u, E, B in reversed(saved):
                 s._call(lib.pic_yee_adjoint(s.ctx, ctypes.byref(lam_f), st), "pic_yee_adjoint")
                 spn = _species_struct(self.q, self.m, self.npart, cell, off, u, self.w)
+                spn.tile_start = self.h.struct.tile_start  # same particle order: the tiled reverse step
                 fn = _fields_struct(E, B, scratch_j)
                 s._call(lib.pic_particle_adjoint(s.ctx, ctypes.byref(spn), ctypes.byref(fn), ctypes.byref(lam_f),
                                                  ctypes.byref(lsp), st), "pic_particle_adjoint")

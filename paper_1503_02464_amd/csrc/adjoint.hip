@@ -101,25 +101,34 @@ __device__ __forceinline__ bool stag(int comp, int d) {
   return (bits[comp] >> d) & 1;
 }
 
-template <typename T, int D, int M>
-__global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= a.np) return;
-  constexpr int K = M + 1;      // gather stencil per axis
-  constexpr int W = M + 2;      // Esirkepov window per axis
-  const uint32_t pk = static_cast<uint32_t>(a.cell[p]);
-  int c[3] = {static_cast<int>(pk & a.mask[0]), static_cast<int>((pk >> a.bits[0]) & a.mask[1]),
-              static_cast<int>((pk >> (a.bits[0] + a.bits[1])) & a.mask[2])};
-#pragma unroll
-  for (int d = 0; d < 3; ++d) c[d] = c[d] >= a.n[d] ? c[d] - a.n[d] : c[d];
-  T o[3], u0[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    o[d] = d < D ? a.off[d][p] : T(0);
-    u0[d] = a.u[d][p];
+// Fields, lamJ and lamE/lamB in HBM (periodic wrap); lamE/lamB by atomics.
+template <typename T>
+struct AdjGlobalF {
+  const AdjArgs<T> &a;
+  __device__ __forceinline__ T load(int comp, int i, int j, int k) const { return a.F[comp][gidx(a.n, i, j, k)]; }
+};
+template <typename T>
+struct AdjGlobalJ {
+  const AdjArgs<T> &a;
+  __device__ __forceinline__ T load(int comp, int i, int j, int k) const { return a.LJ[comp][gidx(a.n, i, j, k)]; }
+};
+template <typename T>
+struct AdjGlobalL {
+  const AdjArgs<T> &a;
+  __device__ __forceinline__ void add(int comp, int i, int j, int k, T v) const {
+    if (v != T(0)) unsafeAtomicAdd(&a.LF[comp][gidx(a.n, i, j, k)], v);
   }
-  const T w = a.w[p];
+};
 
+// The reverse of one particle's step.  c is the particle's cell in the frame
+// of the accessors (global cell for the HBM ones, cell relative to the tile
+// origin for the LDS ones); Fa reads E, B at step n, LJa reads lamJ, LFa adds
+// to lamE, lamB.
+template <typename T, int D, int M, class FA, class JA, class LA>
+__device__ __forceinline__ void adjoint_one(const AdjArgs<T> &a, int64_t p, const int c[3], const T o[3],
+                                            const T u0[3], const T w, const FA &Fa, const JA &LJa, const LA &LFa) {
+  constexpr int K = M + 1;  // gather stencil per axis
+  constexpr int W = M + 2;  // Esirkepov window per axis
   // ---- forward recompute: gather
   T eb[6];
 #pragma unroll
@@ -142,7 +151,7 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
 #pragma unroll
       for (int j = 0; j < K; ++j)
 #pragma unroll
-        for (int i = 0; i < K; ++i) v += a.F[comp][gidx(a.n, b[0] + i, b[1] + j, b[2] + k)] * wt[0][i] * wt[1][j] * wt[2][k];
+        for (int i = 0; i < K; ++i) v += Fa.load(comp, b[0] + i, b[1] + j, b[2] + k) * wt[0][i] * wt[1][j] * wt[2][k];
     eb[comp] = v;
   }
   // ---- forward recompute: Boris with intermediates
@@ -231,7 +240,7 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
               nd[ax] = c[ax] + b[ax] + i;
               nd[bb] = c[bb] + b[bb] + j;
               nd[cc] = c[cc] + b[cc] + k;
-              const T L = a.LJ[ax][gidx(a.n, nd[0], nd[1], nd[2])];
+              const T L = LJa.load(ax, nd[0], nd[1], nd[2]);
               const T Tt = third * (S0[bb][j] * S0[cc][k] + S1[bb][j] * S1[cc][k]) +
                            sixth * (S0[bb][j] * S1[cc][k] + S1[bb][j] * S0[cc][k]);
               gC[i] += -JC * L * Tt;
@@ -275,7 +284,7 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
             int nd[2];
             nd[ax] = c[ax] + b[ax] + i;
             nd[bb] = c[bb] + b[bb] + j;
-            const T L = a.LJ[ax][gidx(a.n, nd[0], nd[1], 0)];
+            const T L = LJa.load(ax, nd[0], nd[1], 0);
             const T A = T(0.5) * (S0[bb][j] + S1[bb][j]);
             gC[i] += -JC * L * A;
             gA[j] += -JC * L * cds;
@@ -301,7 +310,7 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
       for (int i = 0; i < W; ++i)
 #pragma unroll
         for (int j = 0; j < W; ++j) {
-          const T L = a.LJ[2][gidx(a.n, c[0] + b[0] + i, c[1] + b[1] + j, 0)];
+          const T L = LJa.load(2, c[0] + b[0] + i, c[1] + b[1] + j, 0);
           const T Tz = third * (S0[0][i] * S0[1][j] + S1[0][i] * S1[1][j]) +
                        sixth * (S0[0][i] * S1[1][j] + S1[0][i] * S0[1][j]);
           gvz += JZ * L * Tz;
@@ -392,19 +401,142 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a) {
       for (int j = 0; j < K; ++j)
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-          const int64_t g = gidx(a.n, b[0] + i, b[1] + j, b[2] + k);
-          const T Fv = a.F[comp][g];
+          const T Fv = Fa.load(comp, b[0] + i, b[1] + j, b[2] + k);
           lx[0] += leb[comp] * Fv * dw[0][i] * wt[1][j] * wt[2][k];
           lx[1] += leb[comp] * Fv * wt[0][i] * dw[1][j] * wt[2][k];
           if (D == 3) lx[2] += leb[comp] * Fv * wt[0][i] * wt[1][j] * dw[2][k];
           const T v = leb[comp] * wt[0][i] * wt[1][j] * wt[2][k];
-          if (v != T(0)) unsafeAtomicAdd(&a.LF[comp][g], v);
+          LFa.add(comp, b[0] + i, b[1] + j, b[2] + k, v);
         }
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d < D) a.lx[d][p] = lx[d];
     a.lu[d][p] = lum[d];
+  }
+}
+
+// One thread per particle, fields in HBM: every particle (list null) or the
+// listed ones (the stragglers of the tiled pass).
+template <typename T, int D, int M>
+__global__ void __launch_bounds__(256) k_particle_adjoint(AdjArgs<T> a, const int32_t *list, const int32_t *count) {
+  const int64_t n = list ? *count : a.np;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = list ? list[k] : k;
+    if (p < 0 || p >= a.np) continue;
+    const uint32_t pk = static_cast<uint32_t>(a.cell[p]);
+    int c[3] = {static_cast<int>(pk & a.mask[0]), static_cast<int>((pk >> a.bits[0]) & a.mask[1]),
+                static_cast<int>((pk >> (a.bits[0] + a.bits[1])) & a.mask[2])};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) c[d] = c[d] >= a.n[d] ? c[d] - a.n[d] : c[d];
+    T o[3], u0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[d] = d < D ? a.off[d][p] : T(0);
+      u0[d] = a.u[d][p];
+    }
+    adjoint_one<T, D, M>(a, p, c, o, u0, a.w[p], AdjGlobalF<T>{a}, AdjGlobalJ<T>{a}, AdjGlobalL<T>{a});
+  }
+}
+
+// Tile geometry of the tiled adjoint (the fused forward kernel's boxes).
+struct AdjTile {
+  const int32_t *tile_start;  // ranges of the last sort of these particles, in this order
+  int L[3], ntile[3], slack;
+  int rf[3], rj[3];           // field and current box sizes
+  int gf_lo[3], gj_lo[3];     // box origins below the tile origin
+  int32_t *stray_count, *stray_list;
+};
+
+// Full periodic reduction (guard boxes may exceed n on small grids).
+__device__ __forceinline__ int adj_wrap(int i, int n) {
+  const int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+// One workgroup per tile of sorted particles: stage E, B (step n) and lamJ of
+// the tile plus guards in LDS, run the reverse step of every particle within
+// the slack against them, accumulate the gather's transpose in an FP64 LDS
+// box, and add that box to lamE, lamB in HBM.  Particles further out are
+// listed for the HBM kernel.
+template <typename T, int D, int M>
+__global__ void __launch_bounds__(256) k_particle_adjoint_tiled(AdjArgs<T> a, AdjTile t) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t tile = blockIdx.x;
+  int64_t pbeg = t.tile_start[tile], pend = t.tile_start[tile + 1];
+  pbeg = pbeg < 0 ? 0 : (pbeg > a.np ? a.np : pbeg);
+  pend = pend > a.np ? a.np : pend;
+  if (pbeg >= pend) return;
+  const int T0[3] = {static_cast<int>(tile % t.ntile[0]) * t.L[0],
+                     static_cast<int>((tile / t.ntile[0]) % t.ntile[1]) * t.L[1],
+                     static_cast<int>(tile / ((int64_t)t.ntile[0] * t.ntile[1])) * t.L[2]};
+  const int FX = t.rf[0], FY = t.rf[1], FVOL = t.rf[0] * t.rf[1] * t.rf[2];
+  const int JX = t.rj[0], JY = t.rj[1], JVOL = t.rj[0] * t.rj[1] * t.rj[2];
+  double *lfb = reinterpret_cast<double *>(smem_raw);  // [6][FVOL] lamE, lamB
+  T *fb = reinterpret_cast<T *>(lfb + 6 * FVOL);       // [6][FVOL] E, B
+  T *jb = fb + 6 * FVOL;                               // [3][JVOL] lamJ
+  for (int idx = threadIdx.x; idx < FVOL; idx += 256) {
+    const int li = idx % FX, lj = (idx / FX) % FY, lk = idx / (FX * FY);
+    const int64_t g = adj_wrap(T0[0] - t.gf_lo[0] + li, a.n[0]) +
+                      (int64_t)a.n[0] * (adj_wrap(T0[1] - t.gf_lo[1] + lj, a.n[1]) +
+                                         (int64_t)a.n[1] * adj_wrap(T0[2] - t.gf_lo[2] + lk, a.n[2]));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      fb[c * FVOL + idx] = a.F[c][g];
+      lfb[c * FVOL + idx] = 0.0;
+    }
+  }
+  for (int idx = threadIdx.x; idx < JVOL; idx += 256) {
+    const int li = idx % JX, lj = (idx / JX) % JY, lk = idx / (JX * JY);
+    const int64_t g = adj_wrap(T0[0] - t.gj_lo[0] + li, a.n[0]) +
+                      (int64_t)a.n[0] * (adj_wrap(T0[1] - t.gj_lo[1] + lj, a.n[1]) +
+                                         (int64_t)a.n[1] * adj_wrap(T0[2] - t.gj_lo[2] + lk, a.n[2]));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) jb[c * JVOL + idx] = a.LJ[c][g];
+  }
+  __syncthreads();
+  const LdsFields<T> Fa{fb, FX, FX * FY, FVOL, -t.gf_lo[0], -t.gf_lo[1], -t.gf_lo[2]};
+  const LdsFields<T> Ja{jb, JX, JX * JY, JVOL, -t.gj_lo[0], -t.gj_lo[1], -t.gj_lo[2]};
+  const LdsCurrent<double> La{lfb, FX, FX * FY, FVOL, -t.gf_lo[0], -t.gf_lo[1], -t.gf_lo[2]};
+  for (int64_t p = pbeg + threadIdx.x; p < pend; p += 256) {
+    const uint32_t pk = static_cast<uint32_t>(a.cell[p]);
+    int c[3] = {static_cast<int>(pk & a.mask[0]), static_cast<int>((pk >> a.bits[0]) & a.mask[1]),
+                static_cast<int>((pk >> (a.bits[0] + a.bits[1])) & a.mask[2])};
+    // cell relative to the tile origin, unwrapped across the periodic seam
+    int lc[3] = {0, 0, 0};
+    bool inside = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      c[d] = c[d] >= a.n[d] ? c[d] - a.n[d] : c[d];
+      int l = c[d] - T0[d];
+      if (l > a.n[d] / 2) l -= a.n[d];
+      if (l < -a.n[d] / 2) l += a.n[d];
+      lc[d] = l;
+      inside = inside && l >= -t.slack && l < t.L[d] + t.slack;
+    }
+    if (!inside) {
+      t.stray_list[atomicAdd(t.stray_count, 1)] = static_cast<int32_t>(p);
+      continue;
+    }
+    T o[3], u0[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[d] = d < D ? a.off[d][p] : T(0);
+      u0[d] = a.u[d][p];
+    }
+    adjoint_one<T, D, M>(a, p, lc, o, u0, a.w[p], Fa, Ja, La);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < FVOL; idx += 256) {
+    const int li = idx % FX, lj = (idx / FX) % FY, lk = idx / (FX * FY);
+    const int64_t g = adj_wrap(T0[0] - t.gf_lo[0] + li, a.n[0]) +
+                      (int64_t)a.n[0] * (adj_wrap(T0[1] - t.gf_lo[1] + lj, a.n[1]) +
+                                         (int64_t)a.n[1] * adj_wrap(T0[2] - t.gf_lo[2] + lk, a.n[2]));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const T v = static_cast<T>(lfb[c * FVOL + idx]);
+      if (v != T(0)) unsafeAtomicAdd(&a.LF[c][g], v);
+    }
   }
 }
 
@@ -450,8 +582,40 @@ hipError_t particle_adjoint_impl(const pic_ctx &c, const pic_species &sp, const 
   }
   a.jz = static_cast<T>(sp.q / dV);
   a.flags = c.wsp<int32_t>(c.ws.flags);
+  // per tile when the particles' tile ranges are known and the boxes fit in LDS
+  const size_t fvol = static_cast<size_t>(c.rf[0]) * c.rf[1] * c.rf[2];
+  const size_t lds = 6 * fvol * 8 + 6 * fvol * sizeof(T) + 3 * static_cast<size_t>(c.rj[0]) * c.rj[1] * c.rj[2] * sizeof(T);
+  if (sp.tile_start && lds <= kLdsLimit) {
+    AdjTile t{};
+    t.tile_start = sp.tile_start;
+    for (int d = 0; d < 3; ++d) {
+      t.L[d] = c.p.tile[d];
+      t.ntile[d] = c.ntile[d];
+      t.rf[d] = c.rf[d];
+      t.rj[d] = c.rj[d];
+      t.gf_lo[d] = c.gf_lo[d];
+      t.gj_lo[d] = c.gj_lo[d];
+    }
+    t.slack = c.p.slack;
+    t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
+    t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
+    const auto kern = k_particle_adjoint_tiled<T, D, M>;
+    hipError_t e = launch_fill_zero(t.stray_count, 1, 4, st);
+    if (e == hipSuccess && lds > 65536)
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(c.ntiles)), dim3(256), lds, st, a, t);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int64_t sblocks = (sp.np + 255) / 256;
+    if (sblocks > 1024) sblocks = 1024;
+    hipLaunchKernelGGL((k_particle_adjoint<T, D, M>), dim3(static_cast<unsigned>(sblocks)), dim3(256), 0, st, a,
+                       t.stray_list, t.stray_count);
+    return hipGetLastError();
+  }
   const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
-  hipLaunchKernelGGL((k_particle_adjoint<T, D, M>), dim3(blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_particle_adjoint<T, D, M>), dim3(blocks), dim3(256), 0, st, a, nullptr, nullptr);
   return hipGetLastError();
 }
 
