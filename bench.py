@@ -14,7 +14,9 @@ Also printed, in the same JSON line:
   average launch time (HIP events on the launch stream, inside this run),
   against the 8 TB/s HBM peak; traffic = HBM bytes per launch from the
   FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ (null once the
-  kernel sources differ from the ones they were taken on);
+  kernel sources differ from the ones they were taken on); binding = the
+  same record's SQ counters: the fractions of the kernel's cycles the LDS is
+  busy and replaying conflicts, and VALU issue (the kernel is LDS-bound);
 * cpu_baseline: the FP64 CPU oracle, one thread, whole steps of a 64^3 box
   of the same workload (about 10 s);
 * fp64: the same step in FP64 (value and roofline);
@@ -59,10 +61,9 @@ def yee_cell_bytes(prec: str) -> int:
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_push_deposit_thermal3d_256c_8ppc.json")
 
 
-def measured_traffic(w, prec: str):
-    """HBM bytes per launch of the fused kernel from the FETCH_SIZE and
-    WRITE_SIZE counters (scaled by a plain copy of known size), if they were
-    taken on this workload, precision and the current kernel sources; else None."""
+def measured_profile(w, prec: str):
+    """The fused kernel's recorded counters (profiles/), if they were taken on
+    this workload, precision and the current kernel sources; else None."""
     import hashlib
     if prec != "fp32" or w.n != (256, 256, 256):
         return None
@@ -76,9 +77,27 @@ def measured_traffic(w, prec: str):
     except (OSError, KeyError, ValueError):
         return None
     if h.hexdigest() != prof["sha256"]:
-        log("fused kernel sources changed since the traffic counters were taken: traffic = null")
+        log("fused kernel sources changed since the counters were taken: traffic = null")
         return None
-    return int(prof["traffic_bytes_per_launch"])
+    return prof
+
+
+def measured_traffic(w, prec: str):
+    """HBM bytes per launch of the fused kernel from the FETCH_SIZE and
+    WRITE_SIZE counters (scaled by a plain copy of known size), or None."""
+    prof = measured_profile(w, prec)
+    return None if prof is None else int(prof["traffic_bytes_per_launch"])
+
+
+def measured_binding(w, prec: str):
+    """What binds the fused kernel, from its SQ counters (fractions of the
+    kernel's cycles per CU / SIMD), or None: the kernel is limited by LDS
+    throughput (its FP64 LDS current and the gather's LDS reads), not HBM."""
+    prof = measured_profile(w, prec)
+    if prof is None or "lds_active_frac" not in prof:
+        return None
+    return {"unit": "LDS", "lds_active_frac": prof["lds_active_frac"],
+            "lds_bank_conflict_frac": prof["lds_bank_conflict_frac"], "valu_issue_frac": prof["valu_issue_frac"]}
 
 
 def log(msg: str) -> None:
@@ -185,6 +204,7 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(w, prec),
             "bytes_per_launch": per_launch_bytes,
+            "binding": measured_binding(w, prec),
         },
         "yee_cell_updates_per_s": w.ncells / yee_avg_s,
         "yee_achieved_GBs": w.ncells * yee_cell_bytes(prec) / yee_avg_s / 1e9,
