@@ -57,7 +57,8 @@ class Rollout:
         # the fused kernel's tile shapes (16x16 in 2D, 8x8x8 / 8x8x4 in 3D) where they divide the box
         want = (16, 16, 1) if dims == 2 else ((8, 8, 8) if precision == "fp32" else (8, 8, 4))
         tile = tuple(next(t for t in (want[d], 8, 4, 2, 1) if n[d] % t == 0) if d < dims else 1 for d in range(3))
-        self.sim = Simulation(dims, n, dx, dt, order, precision, tile=tile, slack=1, sort_every=0,
+        # slack 2: the particles drift from the tiles of the one sort for the whole rollout
+        self.sim = Simulation(dims, n, dx, dt, order, precision, tile=tile, slack=2, sort_every=0,
                               max_particles=species["w"].shape[0], device=device)
         self.steps = int(steps)
         self.every = int(checkpoint_every)

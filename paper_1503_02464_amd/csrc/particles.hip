@@ -744,6 +744,8 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
   } else {
     if (L[0] == 16 && L[1] == 16 && sl == 1)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sp, f, t, st);
+    else if (L[0] == 16 && L[1] == 16 && sl == 2)  // the rollout, which never re-sorts
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sp, f, t, st);
     else
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sp, f, t, st);
   }
