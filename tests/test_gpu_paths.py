@@ -115,3 +115,27 @@ def test_more_tiles_than_workgroups(prec):
     compare_species(g, prec, s.get_species(h), ref_sp, "queues")
     compare_fields(prec, s.get_fields(), ref_f, what="queues")
     s.close()
+
+
+def test_sort_every_zero_sorts_only_unsorted_species():
+    """sort_every = 0: the first step sorts the unsorted species, later steps
+    keep its order (the array set never swaps again), and four steps still
+    match four oracle steps."""
+    g = grid(3, (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    sp, f = drifting(g, "fp64", 2, (0.3, 0.0, -0.2), seed=650)
+    s = make_sim(g, "fp64", (8, 8, 4), slack=1, sort_every=0, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    assert not h.struct.sorted
+    s.step(1)
+    assert h.struct.sorted
+    cell_ptr, start = h.struct.cell, s.tile_start(h).copy()
+    s.step(3)
+    s.check()
+    assert h.struct.cell == cell_ptr and np.array_equal(s.tile_start(h), start)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    for _ in range(4):
+        assert O.step(g, ref_f, [ref_sp]) == 0
+    compare_species(g, "fp64", s.get_species(h), ref_sp, "sort_every 0")
+    compare_fields("fp64", s.get_fields(), ref_f, what="sort_every 0")
+    s.close()
