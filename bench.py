@@ -335,7 +335,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU spatial decomposition "
-              "is not part of this build", file=sys.stderr)
+              "is not implemented", file=sys.stderr)
         return 2
     import torch
 
