@@ -42,22 +42,30 @@ __device__ __forceinline__ void unpack_cell(int32_t packed, const SortGeom &g, i
 
 // Rank of each lane's key among the active lanes of its wavefront holding the
 // same key, and one atomicAdd per distinct key on counts[]: returns the slot.
+// The groups are found with ballots first, then every group's lowest lane
+// issues its atomic in the same instruction, so a wavefront waits for one
+// atomic round trip however many distinct keys it holds.
 __device__ __forceinline__ int wave_slot(bool active, int key, int32_t *counts) {
   const int lane = __lane_id();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   uint64_t remaining = __ballot(active);
-  int slot = 0;
+  if (!remaining) return 0;
+  uint64_t mine = 0;  // the lanes sharing this lane's key
+  int leader = lane;
   while (remaining) {
-    const int leader = __ffsll(static_cast<unsigned long long>(remaining)) - 1;
-    const int lk = __shfl(key, leader);
+    const int lead = __ffsll(static_cast<unsigned long long>(remaining)) - 1;
+    const int lk = __shfl(key, lead);
     const uint64_t grp = __ballot(active && key == lk);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counts[lk], __popcll(grp));
-    base = __shfl(base, leader);
-    if (active && key == lk) slot = base + __popcll(grp & below);
+    if (active && key == lk) {
+      mine = grp;
+      leader = lead;
+    }
     remaining &= ~grp;
   }
-  return slot;
+  int base = 0;
+  if (active && lane == leader) base = atomicAdd(&counts[key], __popcll(mine));
+  base = __shfl(base, leader);
+  return active ? base + __popcll(mine & below) : 0;
 }
 
 // LDS rank counters of the count pass: nodes hash to kRankSlots counters by
@@ -67,6 +75,7 @@ constexpr int kRankBits = 12;
 constexpr int kRankSlots = 1 << kRankBits;
 constexpr int kCountBlock = 1024;
 constexpr int64_t kCountChunk = 4096;  // particles per workgroup when not sorted
+constexpr int kCountRegs = 5;          // runs up to kCountRegs * kCountBlock particles rank in registers
 // LDS words of the per-level bitmaps over a tile's nodes (and of their prefix
 // counts) that order the particles staying in their tile by node.
 constexpr int kOrderWords = 4096;
@@ -151,26 +160,43 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
     T0[2] = static_cast<int>(b / ((int64_t)g.ntile0 * g.ntile1)) * g.L[2];
   }
   const int64_t dead = (int64_t)g.ntile0 * g.ntile1 * (g.n[2] / g.L[2]) * levels;  // bucket of removed particles
-  for (int64_t base = lo; base < hi; base += kCountBlock) {  // uniform trip count per workgroup
-    const int64_t p = base + threadIdx.x;
-    const bool active = p < hi;
+  // What the count pass reads of particle p: its packed cell, its nearest
+  // node's step per dimension (quadratic shape), and whether it was removed.
+  struct Seen {
+    int32_t cell;
+    bool up[3];
+    bool removed;
+  };
+  auto look = [&](int64_t p, bool active) {
+    Seen v{0, {false, false, false}, false};
+    if (active) {
+      v.cell = cell[p];
+      v.removed = open && w[p] == T(0);
+      if (M == 2) {
+        v.up[0] = o0[p] >= T(0.5);
+        v.up[1] = o1[p] >= T(0.5);
+        v.up[2] = g.dims == 3 && o2[p] >= T(0.5);
+      }
+    }
+    return v;
+  };
+  // First look at particle p (inactive lanes still take part in the ballots):
+  // its key and rank, or a deferred stayer's node.
+  auto first = [&](int64_t p, bool active, const Seen &sv, int32_t &k, int32_t &r) {
     int bucket = -1;
     int kind = 0;  // 0 arrival, 1 stayer with its level, 2 stayer deferred
     int word = 0;
-    if (active && open && w[p] == T(0)) {  // removed at an open face: to the end, out of every tile
+    if (active && sv.removed) {  // removed at an open face: to the end, out of every tile
       bucket = static_cast<int>(dead);
     } else if (active) {
       int c[3];
-      unpack_cell(cell[p], g, c);
+      unpack_cell(sv.cell, g, c);
       const int tile = c[0] / g.L[0] + g.ntile0 * (c[1] / g.L[1] + g.ntile1 * (c[2] / g.L[2]));
       // nearest node (quadratic shape) or cell (linear shape), unwrapped
       int nd[3] = {c[0], c[1], c[2]};
-      if (M == 2) {
-        const T o[3] = {o0[p], o1[p], g.dims == 3 ? o2[p] : T(0)};
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
-          if (d < g.dims && o[d] >= T(0.5)) nd[d] += 1;
-      }
+      for (int d = 0; d < 3; ++d)
+        if (sv.up[d]) nd[d] += 1;
       int level;
       if (order) {
         // previous level: the last segment starting at or before p (the
@@ -203,21 +229,17 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
     }
     const int slot = wave_slot(active && kind == 0, bucket, arrive_count);
     if (active) {
-      key[p] = kind == 1 ? bucket : (kind == 2 ? kDeferred : -bucket - 1);
-      rank[p] = kind == 0 ? slot : word;
+      k = kind == 1 ? bucket : (kind == 2 ? kDeferred : -bucket - 1);
+      r = kind == 0 ? slot : word;
     }
-  }
-  if (!order) return;
-  __syncthreads();
-  // deferred stayers take their node's lowest free level (or overflow into the
-  // last level as arrivals)
-  for (int64_t base = lo; base < hi; base += kCountBlock) {
-    const int64_t p = base + threadIdx.x;
-    const bool deferred = p < hi && key[p] == kDeferred;
+  };
+  // A deferred stayer takes its node's lowest free level (or overflows into
+  // the last level as an arrival).
+  auto defer = [&](bool deferred, int32_t &k, int32_t &r) {
     int v = 0, level = levels - 1;
     bool got = false;
     if (deferred) {
-      v = rank[p];
+      v = r;
       const uint32_t m = 1u << (v & 31);
       for (int l = 0; l < levels - 1 && !got; ++l) {
         if (!(atomicOr(&bits[l * rg.words + (v >> 5)], m) & m)) {
@@ -229,36 +251,111 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
     const int bucket = static_cast<int>(b) * levels + level;
     const int slot = wave_slot(deferred && !got, bucket, arrive_count);
     if (deferred) {
-      key[p] = got ? bucket : -bucket - 1;
-      rank[p] = got ? ((level << kLevelShift) | v) : slot;
+      k = got ? bucket : -bucket - 1;
+      r = got ? ((level << kLevelShift) | v) : slot;
     }
-  }
-  __syncthreads();
-  for (int l = threadIdx.x; l < levels; l += kCountBlock) {  // per level: prefix popcounts, stayer count
-    int run = 0;
-    for (int wd = 0; wd < rg.words; ++wd) {
-      prefix[l * rg.words + wd] = run;
-      run += __popc(bits[l * rg.words + wd]);
+  };
+  // Per level: prefix popcounts of the claim bitmaps and the stayer count.
+  auto level_counts = [&]() {
+    for (int l = threadIdx.x; l < levels; l += kCountBlock) {
+      int run = 0;
+      for (int wd = 0; wd < rg.words; ++wd) {
+        prefix[l * rg.words + wd] = run;
+        run += __popc(bits[l * rg.words + wd]);
+      }
+      stay_count[b * levels + l] = run;
     }
-    stay_count[b * levels + l] = run;
+  };
+  // A stayer's rank in its bucket: the claimed nodes below it in its level.
+  auto node_rank = [&](int32_t r) {
+    const int v = r & ((1 << kLevelShift) - 1);
+    const int wi = (r >> kLevelShift) * rg.words + (v >> 5);
+    return prefix[wi] + __popc(bits[wi] & ((1u << (v & 31)) - 1u));
+  };
+
+  if (hi - lo <= static_cast<int64_t>(kCountBlock) * kCountRegs) {
+    // A run of at most kCountRegs particles per thread keeps its keys and
+    // ranks in registers and stores them once.  The guards on `it` are
+    // uniform over the workgroup.
+    int32_t kk[kCountRegs], rr[kCountRegs];
+    Seen sv[kCountRegs];
+#pragma unroll
+    for (int it = 0; it < kCountRegs; ++it) {  // every load first, then the ranking
+      const int64_t p = lo + static_cast<int64_t>(it) * kCountBlock + threadIdx.x;
+      sv[it] = look(p, p < hi);
+    }
+#pragma unroll
+    for (int it = 0; it < kCountRegs; ++it) {
+      kk[it] = 0;
+      rr[it] = 0;
+      const int64_t p = lo + static_cast<int64_t>(it) * kCountBlock + threadIdx.x;
+      if (lo + static_cast<int64_t>(it) * kCountBlock < hi) first(p, p < hi, sv[it], kk[it], rr[it]);
+    }
+    if (order) {
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kCountRegs; ++it) {
+        const int64_t p = lo + static_cast<int64_t>(it) * kCountBlock + threadIdx.x;
+        if (lo + static_cast<int64_t>(it) * kCountBlock < hi) defer(p < hi && kk[it] == kDeferred, kk[it], rr[it]);
+      }
+      __syncthreads();
+      level_counts();
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < kCountRegs; ++it) {
+        const int64_t p = lo + static_cast<int64_t>(it) * kCountBlock + threadIdx.x;
+        if (p < hi && kk[it] >= 0) rr[it] = node_rank(rr[it]);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < kCountRegs; ++it) {
+      const int64_t p = lo + static_cast<int64_t>(it) * kCountBlock + threadIdx.x;
+      if (p < hi) {
+        key[p] = kk[it];
+        rank[p] = rr[it];
+      }
+    }
+    return;
   }
-  __syncthreads();
-  for (int64_t base = lo; base < hi; base += kCountBlock) {  // stayer ranks: nodes below it in its level
+
+  // Longer runs go through key[] and rank[] in HBM.
+  for (int64_t base = lo; base < hi; base += kCountBlock) {  // uniform trip count per workgroup
     const int64_t p = base + threadIdx.x;
-    if (p < hi && key[p] >= 0) {
-      const int r = rank[p];
-      const int v = r & ((1 << kLevelShift) - 1);
-      const int wi = (r >> kLevelShift) * rg.words + (v >> 5);
-      rank[p] = prefix[wi] + __popc(bits[wi] & ((1u << (v & 31)) - 1u));
+    int32_t k = 0, r = 0;
+    first(p, p < hi, look(p, p < hi), k, r);
+    if (p < hi) {
+      key[p] = k;
+      rank[p] = r;
     }
+  }
+  if (!order) return;
+  __syncthreads();
+  for (int64_t base = lo; base < hi; base += kCountBlock) {
+    const int64_t p = base + threadIdx.x;
+    const bool deferred = p < hi && key[p] == kDeferred;
+    int32_t k = 0, r = deferred ? rank[p] : 0;
+    defer(deferred, k, r);
+    if (deferred) {
+      key[p] = k;
+      rank[p] = r;
+    }
+  }
+  __syncthreads();
+  level_counts();
+  __syncthreads();
+  for (int64_t base = lo; base < hi; base += kCountBlock) {
+    const int64_t p = base + threadIdx.x;
+    if (p < hi && key[p] >= 0) rank[p] = node_rank(rank[p]);
   }
 }
 
 // One workgroup per run (or chunk).  Runs are taken in the order of the
 // previous sort's list of non-empty tiles: dealing the blocks of a sparse box
 // by tile index would pile the busy ones onto a few XCDs and CUs.
+// Eight waves per SIMD let two workgroups share a CU (the pass waits on
+// memory more than it computes).
 template <typename T, int M>
-__global__ void __launch_bounds__(kCountBlock)
+__global__ void __launch_bounds__(kCountBlock) __attribute__((amdgpu_waves_per_eu(8)))
     k_sort_count(const int32_t *cell, const T *o0, const T *o1, const T *o2, const T *w, int open, int64_t np,
                  SortGeom g, RankGeom rg, int levels, const int32_t *runs, const int32_t *hints, int64_t nruns,
                  const int32_t *live, int64_t nitems, int32_t *key, int32_t *rank, int32_t *stay_count,
@@ -380,12 +477,25 @@ __global__ void __launch_bounds__(kScanBlock) k_list_tiles(const int32_t *tile_s
   if (threadIdx.x == 0) live[ntiles] = static_cast<int32_t>(total);
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin.  The copy passes launch a
+// multiple of 8 workgroups and give XCD x the x-th contiguous eighth of the
+// particles, so the lines that neighbouring workgroups share (the reads of a
+// shifted run, the writes of a permuted one) meet in one XCD's L2.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_block() {
+  const int64_t per = gridDim.x / kXcds;
+  return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+}
+
+unsigned xcd_grid(int64_t nblocks) { return static_cast<unsigned>((nblocks + kXcds - 1) / kXcds * kXcds); }
+
 // Pass 3a.  Each particle's slot: a stayer goes to start[bucket] + its node
 // rank, an arrival after the bucket's stayers.  src[slot] = particle.
 __global__ void __launch_bounds__(256) k_sort_slots(int64_t np, const int32_t *key, const int32_t *rank,
                                                    const int32_t *start, const int32_t *stay, int64_t nbuckets,
                                                    int32_t *src, int32_t *flags) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t p = xcd_block() * blockDim.x + threadIdx.x;
   if (p >= np) return;
   const int32_t k = key[p];
   const int64_t bk = k >= 0 ? k : -(int64_t)k - 1;
@@ -407,7 +517,7 @@ __global__ void __launch_bounds__(256) k_sort_gather(int64_t np, const int32_t *
                                                     const T *o0, const T *o1, const T *o2, const T *u0, const T *u1,
                                                     const T *u2, const T *w, int32_t *cell_d, T *o0d, T *o1d,
                                                     T *o2d, T *u0d, T *u1d, T *u2d, T *wd) {
-  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t q = xcd_block() * blockDim.x + threadIdx.x;
   if (q >= np) return;
   const int64_t p = src[q];
   if (p < 0 || p >= np) return;  // only after a flagged inconsistency
@@ -481,7 +591,7 @@ void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_r
 
 template <typename T, int D>
 void reorder(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
-  const unsigned blocks = static_cast<unsigned>((sp.np + 255) / 256);
+  const unsigned blocks = xcd_grid((sp.np + 255) / 256);
   int32_t *src = c.wsp<int32_t>(c.ws.sort_src);
   hipLaunchKernelGGL(k_sort_slots, dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
                      c.wsp<int32_t>(c.ws.sort_rank), start, c.wsp<int32_t>(c.ws.stay_count),
