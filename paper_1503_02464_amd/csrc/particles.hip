@@ -292,6 +292,14 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   int32_t *slot = xn + 1;                                    // the item this workgroup takes next
   // the merge clears the box behind it, so it is zeroed once here
   for (int idx = threadIdx.x; idx < 3 * geo.JVOL; idx += BLOCK) jl[idx] = TJ(0);
+  // A box index T0 - lo + l (0 <= l < X, lo < X, T0 <= n - L) lies in
+  // [-X, n + X).  Where the grid is at least as wide as both boxes along every
+  // axis that is within one period of [0, n), and one conditional add or
+  // subtract wraps it; narrower grids keep the integer modulo.
+  const bool once = g.n[0] >= (geo.FX > geo.JX ? geo.FX : geo.JX) && g.n[1] >= (geo.FY > geo.JY ? geo.FY : geo.JY) &&
+                    (D < 3 || g.n[2] >= (geo.FZ > geo.JZ ? geo.FZ : geo.JZ));
+  const auto near_wrap = [](int i, int n) { return wrap_near(i, n); };
+  const auto full_wrap = [](int i, int n) { return wrap_full(i, n); };
 
   for (int round = 0;; ++round) {
     if (threadIdx.x == 0) {
@@ -324,17 +332,21 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     const int T0[3] = {tx * geo.L0, ty * geo.L1, tz * geo.L2};
 
     // stage E, B of the tile plus guards (periodic wrap)
-    for (int idx = threadIdx.x; idx < geo.FVOL; idx += BLOCK) {
-      const int li = idx % geo.FX;
-      const int lj = (idx / geo.FX) % geo.FY;
-      const int lk = idx / (geo.FX * geo.FY);
-      const int gi = wrap_full(T0[0] - geo.FLO + li, g.n[0]);
-      const int gjj = wrap_full(T0[1] - geo.FLO + lj, g.n[1]);
-      const int gk = D == 3 ? wrap_full(T0[2] - geo.FLO + lk, g.n[2]) : 0;
-      const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
+    auto stage = [&](auto wrap) {
+      for (int idx = threadIdx.x; idx < geo.FVOL; idx += BLOCK) {
+        const int li = idx % geo.FX;
+        const int lj = (idx / geo.FX) % geo.FY;
+        const int lk = idx / (geo.FX * geo.FY);
+        const int gi = wrap(T0[0] - geo.FLO + li, g.n[0]);
+        const int gjj = wrap(T0[1] - geo.FLO + lj, g.n[1]);
+        const int gk = D == 3 ? wrap(T0[2] - geo.FLO + lk, g.n[2]) : 0;
+        const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) fl[c * geo.FVOL + idx] = gf.F[c][gidx];
-    }
+        for (int c = 0; c < 6; ++c) fl[c * geo.FVOL + idx] = gf.F[c][gidx];
+      }
+    };
+    if (once) stage(near_wrap);
+    else stage(full_wrap);
     __syncthreads();
 
     // local frames: the tile origin is (0,0,0)
@@ -529,22 +541,26 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     __syncthreads();
 
     // add the current box into HBM (skipping cells nothing touched)
-    for (int cell = threadIdx.x; cell < geo.JX * geo.JY * geo.JZ; cell += BLOCK) {
-      const int li = cell % geo.JX;
-      const int lj2 = (cell / geo.JX) % geo.JY;
-      const int lk = cell / (geo.JX * geo.JY);
-      const int idx = li + geo.JX * lj2 + geo.JXY * lk;  // the plane stride may be padded
-      const int gi = wrap_full(T0[0] - geo.JLO + li, g.n[0]);
-      const int gjj = wrap_full(T0[1] - geo.JLO + lj2, g.n[1]);
-      const int gk = D == 3 ? wrap_full(T0[2] - geo.JLO + lk, g.n[2]) : 0;
-      const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
+    auto merge = [&](auto wrap) {
+      for (int cell = threadIdx.x; cell < geo.JX * geo.JY * geo.JZ; cell += BLOCK) {
+        const int li = cell % geo.JX;
+        const int lj2 = (cell / geo.JX) % geo.JY;
+        const int lk = cell / (geo.JX * geo.JY);
+        const int idx = li + geo.JX * lj2 + geo.JXY * lk;  // the plane stride may be padded
+        const int gi = wrap(T0[0] - geo.JLO + li, g.n[0]);
+        const int gjj = wrap(T0[1] - geo.JLO + lj2, g.n[1]);
+        const int gk = D == 3 ? wrap(T0[2] - geo.JLO + lk, g.n[2]) : 0;
+        const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
-        jl[c * geo.JVOL + idx] = TJ(0);  // ready for the next tile
-        if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
+        for (int c = 0; c < 3; ++c) {
+          const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
+          jl[c * geo.JVOL + idx] = TJ(0);  // ready for the next tile
+          if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
+        }
       }
-    }
+    };
+    if (once) merge(near_wrap);
+    else merge(full_wrap);
   }
 }
 

@@ -139,3 +139,51 @@ def test_sort_every_zero_sorts_only_unsorted_species():
     compare_species(g, "fp64", s.get_species(h), ref_sp, "sort_every 0")
     compare_fields("fp64", s.get_fields(), ref_f, what="sort_every 0")
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_resort_long_and_short_runs(prec):
+    """The count pass ranks a run of at most 5 x 1024 particles in registers
+    and a longer one through HBM.  A box with 24 particles per cell in its low-x
+    half (6,144 per 8x8x4 tile) and 4 elsewhere (1,024 per tile) takes both;
+    after four pushes the re-sort by the previous runs must be the oracle's tile
+    permutation, and the next push must match the oracle."""
+    g = grid(3, (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    tile = (8, 8, 4)
+    thin = inputs.uniform_plasma(g.n, 3, 4, 0.05, 1.0, 130, u_mean=(0.3, -0.2, 0.1))
+    thick = inputs.uniform_plasma(g.n, 3, 20, 0.05, 1.0, 131, u_mean=(0.3, -0.2, 0.1))
+    keep = thick["cell"][0] < 8
+    sp = dict(thin)
+    for k in ("cell", "off", "u"):
+        sp[k] = np.ascontiguousarray(np.concatenate([thin[k], thick[k][:, keep]], axis=1))
+    sp["w"] = np.ascontiguousarray(np.concatenate([thin["w"], thick["w"][keep]]))
+    sp = inputs.shuffle(sp, 132)
+    sp = unique_weights(sp, 133, scale=float(np.prod(g.dx[:3])) / 12)
+    f = inputs.random_fields(g.ncells, 0.1, 134)
+    if prec == "fp32":
+        sp, f = inputs.round_f32(sp), inputs.round_fields_f32(f)
+    s = make_sim(g, prec, tile, slack=1, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(4)  # the first step sorts (unsorted input, in chunks), the next three only push
+    runs = np.diff(s.tile_start(h))
+    assert runs.max() > 5 * 1024 and 0 < runs.min() <= 5 * 1024, (runs.min(), runs.max())
+    before = s.get_species(h)
+    s.sort(h)
+    out = s.get_species(h)
+    start = s.tile_start(h)
+    ref, ref_start = O.tile_sort(g, tile, before)
+    assert np.array_equal(start, ref_start), "tile offsets differ"
+    keys = O.tile_keys(g, tile, out["cell"])
+    assert np.all(np.diff(keys) >= 0), "keys not sorted"
+    order_a, order_b = np.argsort(out["w"], kind="stable"), np.argsort(ref["w"], kind="stable")
+    assert np.array_equal(out["w"][order_a], ref["w"][order_b])
+    for k in ("cell", "off", "u"):
+        assert np.array_equal(out[k][:, order_a], ref[k][:, order_b]), k
+    ref_sp, ref_f = s.get_species(h), s.get_fields()
+    s.step(1)
+    s.check()
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    compare_species(g, prec, s.get_species(h), ref_sp, "after a re-sort of long and short runs")
+    compare_fields(prec, s.get_fields(), ref_f, what="after a re-sort of long and short runs")
+    s.close()
