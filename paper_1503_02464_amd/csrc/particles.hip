@@ -77,6 +77,94 @@ __device__ __forceinline__ double lane_push(int to, double v) {
   return __hiloint2double(hi, lo);
 }
 
+// The Esirkepov deposit (3D) of a particle whose nearest node (cell, for the
+// linear shape) changed along at least one axis, into the LDS current box
+// jl (origin -jlo, strides 1, jx, jxy, component stride jvol).  The current
+// along each axis depends symmetrically on the two axes across it, so a
+// cyclic relabelling of the axes leaves it unchanged.  Each lane relabels
+// its axes so that one it crossed comes first: that axis takes the wide
+// window (M + 2 nodes) in every lane, the other two take M + 1 nodes, or
+// M + 2 where they crossed as well (rare).  A wavefront of such particles
+// then runs one set of loops: 75 adds per particle for the quadratic shape
+// (20 for the linear one) where the general form issues 144 (54) divergent,
+// zero-tested slots.  The nodes it skips carry exact zeros.  Every add goes
+// through per-lane strides.
+template <typename T, int M, typename S>
+__device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jvol, int jlo, const int c0[3],
+                                                  const T o0[3], const int dc[3], const T o1[3], const T jc[3]) {
+  constexpr int WN = M + 1, WW = M + 2;  // narrow and wide node counts
+  bool cr[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if constexpr (M == 2) {
+      const int n0 = o0[d] >= T(0.5) ? 1 : 0;
+      cr[d] = dc[d] + (o1[d] >= T(0.5) ? 1 : 0) != n0;
+    } else {
+      cr[d] = dc[d] != 0;
+    }
+  }
+  const int a = cr[0] ? 0 : (cr[1] ? 1 : 2);  // the leading axis: one that was crossed
+  const int ax[3] = {a, a == 2 ? 0 : a + 1, a == 0 ? 2 : a - 1};
+  T p0[3], p1[3], pc[3];
+  int pdc[3], st[3], cb[3];
+  bool wide[3];
+  int org = 0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int d = ax[r];
+    p0[r] = d == 0 ? o0[0] : (d == 1 ? o0[1] : o0[2]);
+    p1[r] = d == 0 ? o1[0] : (d == 1 ? o1[1] : o1[2]);
+    pdc[r] = d == 0 ? dc[0] : (d == 1 ? dc[1] : dc[2]);
+    pc[r] = d == 0 ? jc[0] : (d == 1 ? jc[1] : jc[2]);
+    st[r] = d == 0 ? 1 : (d == 1 ? jx : jxy);
+    cb[r] = d * jvol;
+    wide[r] = d == 0 ? cr[0] : (d == 1 ? cr[1] : cr[2]);
+  }
+  Esirk<T, M> e;
+  esirkepov_factors<T, 3, M>(p0, pdc, p1, e);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const int d = ax[r];
+    org += st[r] * ((d == 0 ? c0[0] : (d == 1 ? c0[1] : c0[2])) + e.b[r] + jlo);
+  }
+  // along the leading axis: its M + 1 edges, nodes across
+#pragma unroll
+  for (int k = 0; k < WW; ++k)
+    if (k < WN || wide[2])
+#pragma unroll
+      for (int j = 0; j < WW; ++j)
+        if (j < WN || wide[1]) {
+          const T t = e.A[1][j] * e.S0[2][k] + e.Bf[1][j] * e.DS[2][k];
+#pragma unroll
+          for (int i = 0; i < WW - 1; ++i)
+            atomicAdd(&jl[cb[0] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[0] * e.CDS[0][i] * t));
+        }
+  // along the second axis
+#pragma unroll
+  for (int k = 0; k < WW; ++k)
+    if (k < WN || wide[2])
+#pragma unroll
+      for (int i = 0; i < WW; ++i) {
+        const T t = e.A[0][i] * e.S0[2][k] + e.Bf[0][i] * e.DS[2][k];
+#pragma unroll
+        for (int j = 0; j < WW - 1; ++j)
+          if (j < WN - 1 || wide[1])
+            atomicAdd(&jl[cb[1] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[1] * e.CDS[1][j] * t));
+      }
+  // along the third axis
+#pragma unroll
+  for (int j = 0; j < WW; ++j)
+    if (j < WN || wide[1])
+#pragma unroll
+      for (int i = 0; i < WW; ++i) {
+        const T t = e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j];
+#pragma unroll
+        for (int k = 0; k < WW - 1; ++k)
+          if (k < WN - 1 || wide[2])
+            atomicAdd(&jl[cb[2] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[2] * e.CDS[2][k] * t));
+      }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_particle(const SpeciesArgs<T> &s, int64_t p, T o[3], T u[3]) {
 #pragma unroll
@@ -533,10 +621,14 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       }
       unpack_local(xk[k], lc, dc);
       const T w = xw[k];
-      Esirk<T, M> e;
-      esirkepov_factors<T, D, M>(o0, dc, o1, e);
       const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-      esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
+      if constexpr (D == 3) {
+        esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc);
+      } else {
+        Esirk<T, M> e;
+        esirkepov_factors<T, D, M>(o0, dc, o1, e);
+        esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
+      }
     }
     __syncthreads();
 
