@@ -165,6 +165,65 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
       }
 }
 
+// The same in 2D3V: the axes x and y swap when only y was crossed.  J_z,
+// the time-averaged shape product times v_z, is symmetric in them too.  29
+// adds per particle for the quadratic shape (12 for the linear one) where the
+// general form issues 40 (21) zero-tested slots.
+template <typename T, int M, typename S>
+__device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, int jlo, const int c0[3],
+                                                     const T o0[3], const int dc[3], const T o1[3], const T jc[3],
+                                                     T jzc) {
+  constexpr int WN = M + 1, WW = M + 2;
+  bool cr[2];
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    if constexpr (M == 2) {
+      const int n0 = o0[d] >= T(0.5) ? 1 : 0;
+      cr[d] = dc[d] + (o1[d] >= T(0.5) ? 1 : 0) != n0;
+    } else {
+      cr[d] = dc[d] != 0;
+    }
+  }
+  const bool sw = !cr[0];  // lead with y
+  const T p0[3] = {sw ? o0[1] : o0[0], sw ? o0[0] : o0[1], T(0)};
+  const T p1[3] = {sw ? o1[1] : o1[0], sw ? o1[0] : o1[1], T(0)};
+  const int pdc[3] = {sw ? dc[1] : dc[0], sw ? dc[0] : dc[1], 0};
+  const T pc[2] = {sw ? jc[1] : jc[0], sw ? jc[0] : jc[1]};
+  const int st[2] = {sw ? jx : 1, sw ? 1 : jx};
+  const int cb[2] = {sw ? jvol : 0, sw ? 0 : jvol};
+  const bool wide1 = sw ? cr[0] : cr[1];
+  Esirk<T, M> e;
+  esirkepov_factors<T, 2, M>(p0, pdc, p1, e);
+  const int org = st[0] * ((sw ? c0[1] : c0[0]) + e.b[0] + jlo) + st[1] * ((sw ? c0[0] : c0[1]) + e.b[1] + jlo);
+  // along the leading axis
+#pragma unroll
+  for (int j = 0; j < WW; ++j)
+    if (j < WN || wide1) {
+      const T t = e.A[1][j];
+#pragma unroll
+      for (int i = 0; i < WW - 1; ++i)
+        atomicAdd(&jl[cb[0] + org + i * st[0] + j * st[1]], static_cast<S>(-pc[0] * e.CDS[0][i] * t));
+    }
+  // along the other in-plane axis
+#pragma unroll
+  for (int i = 0; i < WW; ++i) {
+    const T t = e.A[0][i];
+#pragma unroll
+    for (int j = 0; j < WW - 1; ++j)
+      if (j < WN - 1 || wide1)
+        atomicAdd(&jl[cb[1] + org + i * st[0] + j * st[1]], static_cast<S>(-pc[1] * e.CDS[1][j] * t));
+  }
+  // out of the plane
+  if (jzc != T(0))
+#pragma unroll
+    for (int j = 0; j < WW; ++j)
+      if (j < WN || wide1)
+#pragma unroll
+        for (int i = 0; i < WW; ++i)
+          atomicAdd(&jl[2 * jvol + org + i * st[0] + j * st[1]],
+                    static_cast<S>(jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j])));
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void load_particle(const SpeciesArgs<T> &s, int64_t p, T o[3], T u[3]) {
 #pragma unroll
@@ -622,13 +681,10 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       unpack_local(xk[k], lc, dc);
       const T w = xw[k];
       const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-      if constexpr (D == 3) {
+      if constexpr (D == 3)
         esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc);
-      } else {
-        Esirk<T, M> e;
-        esirkepov_factors<T, D, M>(o0, dc, o1, e);
-        esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * xw[CAP + k]);
-      }
+      else
+        esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, w * xw[CAP + k]);
     }
     __syncthreads();
 
