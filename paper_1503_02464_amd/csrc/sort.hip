@@ -141,13 +141,14 @@ __device__ __forceinline__ void count_run(int64_t b, CountLds &sh, const int32_t
     // previous level segments, clamped to partition [lo, hi): segment l
     // starts at the largest of the first l + 1 hinted starts (the first is
     // lo), at most hi
-    if (threadIdx.x < levels) raw[threadIdx.x] = threadIdx.x == 0 ? lo : hints[b * levels + threadIdx.x];
+    const int t = static_cast<int>(threadIdx.x);
+    if (t < levels) raw[t] = t == 0 ? lo : hints[b * levels + t];
     __syncthreads();
-    if (threadIdx.x <= levels) {
+    if (t <= levels) {
       int64_t v = lo;
-      if (threadIdx.x < levels)
-        for (int l = 0; l <= static_cast<int>(threadIdx.x); ++l) v = raw[l] > v ? raw[l] : v;
-      seg[threadIdx.x] = threadIdx.x < levels && v < hi ? v : hi;
+      if (t < levels)
+        for (int l = 0; l <= t; ++l) v = raw[l] > v ? raw[l] : v;
+      seg[t] = t < levels && v < hi ? v : hi;
     }
   } else {
     for (int i = threadIdx.x; i < kRankSlots; i += kCountBlock) counter[i] = 0;
