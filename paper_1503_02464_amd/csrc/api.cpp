@@ -399,23 +399,25 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
   hipError_t e = hipSuccess;
   for (int it = 0; it < nsteps; ++it) {
     const bool cadence = c->p.sort_every > 0 && (c->step % c->p.sort_every) == 0;
-    for (int i = 0; i < nspecies; ++i) {
-      if (sp[i].np > 0 && (cadence || !sp[i].sorted)) {
-        PhaseTimer t(c, s, pic::kPhaseSort);
-        e = pic::launch_sort(*c, sp[i], s);
-        if (e != hipSuccess) return hip_fail(c, e, "sort");
-      }
-    }
     {
       PhaseTimer t(c, s, pic::kPhaseZero);
       for (int d = 0; d < 3 && e == hipSuccess; ++d) e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, s);
       if (e == hipSuccess && c->has_laser) e = pic::launch_laser(*c, *f, (c->step + 0.5) * c->p.dt, s);
       if (e != hipSuccess) return hip_fail(c, e, "zero_current");
     }
+    // Species by species: a sort ranks the particles and leaves its copy into
+    // the second array set to the push that follows it, which reads each
+    // particle through the sort's slots and writes it in sorted order.
     for (int i = 0; i < nspecies; ++i) {
       if (sp[i].np == 0) continue;
+      const int32_t *src = nullptr;
+      if (cadence || !sp[i].sorted) {
+        PhaseTimer t(c, s, pic::kPhaseSort);
+        e = pic::launch_sort(*c, sp[i], s, &src);
+        if (e != hipSuccess) return hip_fail(c, e, "sort");
+      }
       PhaseTimer t(c, s, pic::kPhasePush);
-      e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s);
+      e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s, src);
       if (e != hipSuccess) return hip_fail(c, e, "push_deposit");
     }
     {

@@ -23,6 +23,14 @@ struct SpeciesArgs {
   T dtdx[3];    // dt / dx_d
   T jc[3];      // (q / dV)(dx_d / dt), times w per particle
   T jz;         // q / dV (2D J_z), times w v_z per particle
+  // The fused kernel reads particle q at src[q] when src is set (a sort whose
+  // copy it takes over) and writes it to the *_o arrays, which otherwise are
+  // the arrays above.
+  const int32_t *src;
+  int32_t *cell_o;
+  T *off_o[3];
+  T *u_o[3];
+  T *w_o;
 };
 
 struct GridArgs {
@@ -510,20 +518,29 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     int64_t pn = pbeg + threadIdx.x;
     int32_t n_cell = 0;
     T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
-    if (pn < pend) {
-      n_cell = s.cell[pn];
-      n_w = s.w[pn];
-      load_particle<T, D>(s, pn, n_o, n_u);
+    // where particle q is read from: itself, or src[q] after a sort whose
+    // copy this launch takes over (-1: a slot that sort left inconsistent, flagged)
+    auto from = [&](int64_t q) -> int64_t {
+      if (!s.src) return q;
+      const int64_t r = s.src[q];
+      return r >= 0 && r < s.np ? r : -1;
+    };
+    int64_t n_r = pn < pend ? from(pn) : -1;
+    if (n_r >= 0) {
+      n_cell = s.cell[n_r];
+      n_w = s.w[n_r];
+      load_particle<T, D>(s, n_r, n_o, n_u);
     }
     for (int64_t trip = 0; trip < trips; ++trip, pn += BLOCK) {
       const int32_t p_cell = n_cell;
       const T w = n_w;
       T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
-      const bool have = pn < pend;
-      if (pn + BLOCK < pend) {
-        n_cell = s.cell[pn + BLOCK];
-        n_w = s.w[pn + BLOCK];
-        load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
+      const bool have = pn < pend && n_r >= 0;
+      n_r = pn + BLOCK < pend ? from(pn + BLOCK) : -1;
+      if (n_r >= 0) {
+        n_cell = s.cell[n_r];
+        n_w = s.w[n_r];
+        load_particle<T, D>(s, n_r, n_o, n_u);
       }
       const int64_t p = pn;
       int c[3] = {0, 0, 0};
@@ -657,13 +674,22 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-          s.off[d][p] = on[d];
+          s.off_o[d][p] = on[d];
         }
-        s.cell[p] = pack(c, g);
-        s.u[0][p] = u[0];
-        s.u[1][p] = u[1];
-        s.u[2][p] = u[2];
-        absorb_if_out(s, p, c[0]);
+        s.cell_o[p] = pack(c, g);
+        s.u_o[0][p] = u[0];
+        s.u_o[1][p] = u[1];
+        s.u_o[2][p] = u[2];
+        if (s.open && (c[0] < s.xlo || c[0] >= s.xhi)) s.w_o[p] = T(0);  // removed at an open face
+        else if (s.src) s.w_o[p] = w;
+      } else if (have && s.src) {  // a straggler or a removed particle moves unchanged
+#pragma unroll
+        for (int d = 0; d < D; ++d) s.off_o[d][p] = o[d];
+        s.cell_o[p] = p_cell;
+        s.u_o[0][p] = u[0];
+        s.u_o[1][p] = u[1];
+        s.u_o[2][p] = u[2];
+        s.w_o[p] = w;
       }
     }
     __syncthreads();
@@ -751,6 +777,25 @@ __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g
   }
 }
 
+// After a fused launch that took over a sort's copy: the particles behind
+// every tile (the bucket of removed ones, [tile_start[ntiles], np)) move to
+// the second set unchanged.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_fold_tail(SpeciesArgs<T> s, const int32_t *tile_start, int64_t ntiles) {
+  int64_t lo = tile_start[ntiles];
+  lo = lo < 0 ? 0 : lo;
+  for (int64_t q = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < s.np; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = s.src[q];
+    if (r < 0 || r >= s.np) continue;  // only after a flagged inconsistency
+    s.cell_o[q] = s.cell[r];
+#pragma unroll
+    for (int d = 0; d < D; ++d) s.off_o[d][q] = s.off[d][r];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s.u_o[d][q] = s.u[d][r];
+    s.w_o[q] = s.w[r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side argument assembly and dispatch.
 // ---------------------------------------------------------------------------
@@ -764,6 +809,13 @@ SpeciesArgs<T> species_args(const pic_ctx &c, const pic_species &sp) {
     s.u[d] = static_cast<T *>(sp.u[d]);
   }
   s.w = static_cast<T *>(sp.w);
+  s.src = nullptr;
+  s.cell_o = s.cell;
+  for (int d = 0; d < 3; ++d) {
+    s.off_o[d] = s.off[d];
+    s.u_o[d] = s.u[d];
+  }
+  s.w_o = s.w;
   s.open = c.p.open_x;
   s.xlo = c.p.open_x ? c.p.absorb : 0;
   s.xhi = c.p.open_x ? static_cast<int>(c.n[0]) - c.p.absorb : static_cast<int>(c.n[0]);
@@ -834,7 +886,7 @@ hipError_t deposit_impl(const pic_ctx &c, const pic_species &sp, const pic_field
 }
 
 template <typename T, int D, int M, class G, int BLOCK, typename TJ>
-hipError_t launch_tiled_acc(const pic_ctx &c, const pic_species &sp, const pic_fields &f, const TileArgs &t,
+hipError_t launch_tiled_acc(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                             hipStream_t st) {
   const auto kern = k_push_deposit_tiled<T, D, M, G, BLOCK, TJ>;
   const size_t lds = c.lds_bytes;
@@ -853,27 +905,37 @@ hipError_t launch_tiled_acc(const pic_ctx &c, const pic_species &sp, const pic_f
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   int64_t blocks = static_cast<int64_t>(ncu) * per_cu;
   if (blocks > c.ntiles) blocks = c.ntiles;
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), lds, st, species_args<T>(c, sp),
-                     grid_args(c), global_fields<T>(c, f), global_current<T>(c, f), t, c.wsp<int32_t>(c.ws.flags));
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(blocks)), dim3(BLOCK), lds, st, sa, grid_args(c),
+                     global_fields<T>(c, f), global_current<T>(c, f), t, c.wsp<int32_t>(c.ws.flags));
   return hipGetLastError();
 }
 
 // The LDS current box is accumulated in double unless the caller asked for
 // FP32 accumulation of an FP32 state.
 template <typename T, int D, int M, class G, int BLOCK>
-hipError_t launch_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, const TileArgs &t,
+hipError_t launch_tiled(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                         hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
-    if (!c.acc64) return launch_tiled_acc<T, D, M, G, BLOCK, float>(c, sp, f, t, st);
+    if (!c.acc64) return launch_tiled_acc<T, D, M, G, BLOCK, float>(c, sa, f, t, st);
   }
-  return launch_tiled_acc<T, D, M, G, BLOCK, double>(c, sp, f, t, st);
+  return launch_tiled_acc<T, D, M, G, BLOCK, double>(c, sa, f, t, st);
 }
 
 // Tile shapes with a compile-time instantiation; other shapes use the
 // runtime-geometry kernel.
 template <typename T, int D, int M>
-hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t st) {
+hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t st, const int32_t *src) {
   if (sp.np == 0) return hipSuccess;
+  SpeciesArgs<T> sa = species_args<T>(c, sp);
+  if (src) {  // read through the sort's slots, write the second set
+    sa.src = src;
+    sa.cell_o = sp.cell_alt;
+    for (int d = 0; d < 3; ++d) {
+      sa.off_o[d] = static_cast<T *>(sp.off_alt[d]);
+      sa.u_o[d] = static_cast<T *>(sp.u_alt[d]);
+    }
+    sa.w_o = static_cast<T *>(sp.w_alt);
+  }
   TileArgs t{};
   t.tile_start = sp.tile_start;
   for (int d = 0; d < 3; ++d) {
@@ -900,22 +962,29 @@ hipError_t tiled_impl(const pic_ctx &c, const pic_species &sp, const pic_fields 
   constexpr int BIG = sizeof(T) == 4 ? 1024 : 512;  // threads per workgroup of the fixed-shape kernels
   if constexpr (D == 3) {
     if (sizeof(T) == 4 && L[0] == 8 && L[1] == 8 && L[2] == 8 && sl == 1)
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 8, 1>, BIG>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 8, 1>, BIG>(c, sa, f, t, st);
     else if (L[0] == 8 && L[1] == 8 && L[2] == 4 && sl == 1)
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 4, 1>, BIG>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 4, 1>, BIG>(c, sa, f, t, st);
     else
-      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   } else {
     if (L[0] == 16 && L[1] == 16 && sl == 1)
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sa, f, t, st);
     else if (L[0] == 16 && L[1] == 16 && sl == 2)  // the rollout, which never re-sorts
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sa, f, t, st);
     else
-      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sp, f, t, st);
+      e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   }
   if (e != hipSuccess) return e;
   int64_t blocks = (sp.np + 255) / 256;
   if (blocks > 1024) blocks = 1024;
+  if (src) {  // the removed particles behind every tile, then the sets swap
+    hipLaunchKernelGGL((k_fold_tail<T, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, sa,
+                       sp.tile_start, c.ntiles);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    swap_sets(sp);
+  }
   hipLaunchKernelGGL((k_stragglers<T, D, M>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
                      species_args<T>(c, sp), grid_args(c), global_fields<T>(c, f), global_current<T>(c, f),
                      t.stray_count, t.stray_list, c.wsp<int32_t>(c.ws.flags));
@@ -951,8 +1020,9 @@ hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fie
   PIC_DISPATCH(deposit_impl, c, sp, f, s);
 }
 
-hipError_t launch_push_deposit_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s) {
-  PIC_DISPATCH(tiled_impl, c, sp, f, s);
+hipError_t launch_push_deposit_tiled(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t s,
+                                     const int32_t *src) {
+  PIC_DISPATCH(tiled_impl, c, sp, f, s, src);
 }
 
 }  // namespace pic

@@ -121,7 +121,11 @@ namespace pic {
 // error of its launches.
 hipError_t launch_gather_push(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
-hipError_t launch_push_deposit_tiled(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
+// src: when not null, the slots of a sort whose copy was left to this launch
+// (particle q of the sorted order is particle src[q] of the current set); the
+// launch writes every particle into the second set and swaps the sets.
+hipError_t launch_push_deposit_tiled(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t s,
+                                     const int32_t *src = nullptr);
 hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
 // Open x faces: save = true keeps E_y, E_z^n next to the faces (before the E
 // update), save = false applies the Mur update to the faces (after it).
@@ -136,7 +140,10 @@ hipError_t launch_scale_copy(const pic_ctx &c, void *const dst[3], const void *c
                              hipStream_t s);
 hipError_t launch_particle_adjoint(const pic_ctx &c, const pic_species &sp, const pic_fields &f,
                                    const pic_fields &lam, const pic_species_adjoint &lsp, hipStream_t s);
-hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s);
+// fold_src: when not null, the copy into the second set is left to the next
+// fused push (*fold_src receives the slots; null if the sort copied anyway).
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src = nullptr);
+void swap_sets(pic_species &sp);
 // The non-empty tiles of a species' last sort (list, count at [ntiles]), or
 // null when this context has not sorted that species.
 const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp);

@@ -590,13 +590,15 @@ void count(const pic_ctx &c, const pic_species &sp, const SortGeom &g, bool by_r
                        arrive);
 }
 
+// Slots, then (copy) the gather into the second set.
 template <typename T, int D>
-void reorder(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipStream_t s) {
+void reorder(const pic_ctx &c, const pic_species &sp, const int32_t *start, bool copy, hipStream_t s) {
   const unsigned blocks = xcd_grid((sp.np + 255) / 256);
   int32_t *src = c.wsp<int32_t>(c.ws.sort_src);
   hipLaunchKernelGGL(k_sort_slots, dim3(blocks), dim3(256), 0, s, sp.np, c.wsp<int32_t>(c.ws.sort_key),
                      c.wsp<int32_t>(c.ws.sort_rank), start, c.wsp<int32_t>(c.ws.stay_count),
                      c.ntiles * c.levels + 1, src, c.wsp<int32_t>(c.ws.flags));
+  if (!copy) return;
   hipLaunchKernelGGL((k_sort_gather<T, D>), dim3(blocks), dim3(256), 0, s, sp.np, src, sp.cell,
                      static_cast<const T *>(sp.off[0]), static_cast<const T *>(sp.off[1]),
                      static_cast<const T *>(sp.off[2]), static_cast<const T *>(sp.u[0]),
@@ -609,10 +611,19 @@ void reorder(const pic_ctx &c, const pic_species &sp, const int32_t *start, hipS
 
 }  // namespace
 
+void swap_sets(pic_species &sp) {
+  std::swap(sp.cell, sp.cell_alt);
+  for (int d = 0; d < 3; ++d) {
+    std::swap(sp.off[d], sp.off_alt[d]);
+    std::swap(sp.u[d], sp.u_alt[d]);
+  }
+  std::swap(sp.w, sp.w_alt);
+}
+
 int64_t sort_scan_blocks(int64_t nbuckets) { return (nbuckets + kScanTile - 1) / kScanTile; }
 int64_t sort_scan_capacity() { return static_cast<int64_t>(kScanBlock) * kScanItems; }
 
-hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src) {
   // buckets: (tile, level) for every tile, then one for removed particles
   const int64_t nb = c.ntiles * c.levels + 1;
   int32_t *stay = c.wsp<int32_t>(c.ws.stay_count);
@@ -670,22 +681,22 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, stay, arrive, nb,
                      partials, c.levels, start, sp.tile_start, c.ntiles);
   hipLaunchKernelGGL(k_list_tiles, dim3(1), dim3(kScanBlock), 0, s, sp.tile_start, c.ntiles, live);
+  const bool copy = fold_src == nullptr || sp.np == 0;
   if (sp.np > 0) {
     const bool f64 = c.p.precision == PIC_FP64;
     if (f64)
-      (c.p.dims == 3) ? reorder<double, 3>(c, sp, start, s) : reorder<double, 2>(c, sp, start, s);
+      (c.p.dims == 3) ? reorder<double, 3>(c, sp, start, copy, s) : reorder<double, 2>(c, sp, start, copy, s);
     else
-      (c.p.dims == 3) ? reorder<float, 3>(c, sp, start, s) : reorder<float, 2>(c, sp, start, s);
+      (c.p.dims == 3) ? reorder<float, 3>(c, sp, start, copy, s) : reorder<float, 2>(c, sp, start, copy, s);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // the sorted data now lives in the second set: swap the sets
-  std::swap(sp.cell, sp.cell_alt);
-  for (int d = 0; d < 3; ++d) {
-    std::swap(sp.off[d], sp.off_alt[d]);
-    std::swap(sp.u[d], sp.u_alt[d]);
+  if (copy) {
+    if (fold_src) *fold_src = nullptr;
+    swap_sets(sp);  // the sorted data now lives in the second set
+  } else {
+    *fold_src = c.wsp<int32_t>(c.ws.sort_src);  // the caller's push copies, then swaps
   }
-  std::swap(sp.w, sp.w_alt);
   sp.sorted = 1;
   c.sorted_runs[slot].second = sp.np;
   return hipSuccess;
