@@ -227,9 +227,9 @@ pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
  * species, or every sort_every steps when sort_every > 0) and run the fused
  * gather + push + deposit per tile with fields and current staged on chip
  * (and, with open_x, removal of the particles that left); then the Yee
- * update.  After a sort the push reads each particle through the sort's
- * slots and writes it into the second array set, which then becomes the
- * current one: the same swap and tile_start as pic_sort gives. */
+ * update.  In 3D, after a sort the push reads each particle through the
+ * sort's slots and writes it into the second array set, which then becomes
+ * the current one: the same swap and tile_start as pic_sort gives. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields *f, int32_t nsteps, void *stream);
 
 /* FP64 diagnostics of the current state, accumulated in double on the device,

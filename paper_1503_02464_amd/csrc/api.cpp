@@ -405,15 +405,18 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
       if (e == hipSuccess && c->has_laser) e = pic::launch_laser(*c, *f, (c->step + 0.5) * c->p.dt, s);
       if (e != hipSuccess) return hip_fail(c, e, "zero_current");
     }
-    // Species by species: a sort ranks the particles and leaves its copy into
-    // the second array set to the push that follows it, which reads each
-    // particle through the sort's slots and writes it in sorted order.
+    // Species by species.  In 3D a sort ranks the particles and leaves its
+    // copy into the second array set to the push that follows it, which reads
+    // each particle through the sort's slots and writes it in sorted order.
+    // The 2D push has too little work per particle to hide the extra read, so
+    // there the sort copies.
+    const bool fold = c->p.dims == 3;
     for (int i = 0; i < nspecies; ++i) {
       if (sp[i].np == 0) continue;
       const int32_t *src = nullptr;
       if (cadence || !sp[i].sorted) {
         PhaseTimer t(c, s, pic::kPhaseSort);
-        e = pic::launch_sort(*c, sp[i], s, &src);
+        e = pic::launch_sort(*c, sp[i], s, fold ? &src : nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "sort");
       }
       PhaseTimer t(c, s, pic::kPhasePush);
