@@ -412,12 +412,19 @@ struct CurrentBox<T, RuntimeGeom, DD> {
 // cell lies within the slack of the tile (gather from LDS, Boris, move,
 // Esirkepov into an LDS current box held in TJ), then add the current box
 // into J in HBM.  Particles further out are listed for k_stragglers.
-template <typename T, int D, int M, class G, int BLOCK, typename TJ>
+// FOLD: the launch takes over a sort's copy (reads through s.src, writes the
+// *_o arrays); otherwise it updates the particles in place and never touches
+// those pointers, which keeps them out of the registers.
+template <typename T, int D, int M, class G, int BLOCK, typename TJ, bool FOLD>
 __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                               GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *smem = reinterpret_cast<T *>(smem_raw);
   const G geo(t);
+  int32_t *const cell_o = FOLD ? s.cell_o : s.cell;
+  T *const off_o[3] = {FOLD ? s.off_o[0] : s.off[0], FOLD ? s.off_o[1] : s.off[1], FOLD ? s.off_o[2] : s.off[2]};
+  T *const u_o[3] = {FOLD ? s.u_o[0] : s.u[0], FOLD ? s.u_o[1] : s.u[1], FOLD ? s.u_o[2] : s.u[2]};
+  T *const w_o = FOLD ? s.w_o : s.w;
   // Work items are the non-empty tiles (all tiles when no list is known).
   // Workgroups are dealt to the 8 XCDs round-robin.  Each XCD owns a
   // contiguous range of items, so that neighbouring tiles share its L2.  A
@@ -518,29 +525,42 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     int64_t pn = pbeg + threadIdx.x;
     int32_t n_cell = 0;
     T n_w = T(0), n_o[3] = {T(0), T(0), T(0)}, n_u[3] = {T(0), T(0), T(0)};
-    // where particle q is read from: itself, or src[q] after a sort whose
-    // copy this launch takes over (-1: a slot that sort left inconsistent, flagged)
+    // FOLD: particle q of the sorted order is read at src[q] (-1: a slot the
+    // sort left inconsistent, which it flagged)
     auto from = [&](int64_t q) -> int64_t {
-      if (!s.src) return q;
       const int64_t r = s.src[q];
       return r >= 0 && r < s.np ? r : -1;
     };
-    int64_t n_r = pn < pend ? from(pn) : -1;
-    if (n_r >= 0) {
-      n_cell = s.cell[n_r];
-      n_w = s.w[n_r];
-      load_particle<T, D>(s, n_r, n_o, n_u);
+    int64_t n_r = -1;
+    if constexpr (FOLD) {
+      n_r = pn < pend ? from(pn) : -1;
+      if (n_r >= 0) {
+        n_cell = s.cell[n_r];
+        n_w = s.w[n_r];
+        load_particle<T, D>(s, n_r, n_o, n_u);
+      }
+    } else if (pn < pend) {
+      n_cell = s.cell[pn];
+      n_w = s.w[pn];
+      load_particle<T, D>(s, pn, n_o, n_u);
     }
     for (int64_t trip = 0; trip < trips; ++trip, pn += BLOCK) {
       const int32_t p_cell = n_cell;
       const T w = n_w;
       T o[3] = {n_o[0], n_o[1], n_o[2]}, u[3] = {n_u[0], n_u[1], n_u[2]};
-      const bool have = pn < pend && n_r >= 0;
-      n_r = pn + BLOCK < pend ? from(pn + BLOCK) : -1;
-      if (n_r >= 0) {
-        n_cell = s.cell[n_r];
-        n_w = s.w[n_r];
-        load_particle<T, D>(s, n_r, n_o, n_u);
+      bool have = pn < pend;
+      if constexpr (FOLD) {
+        have = have && n_r >= 0;
+        n_r = pn + BLOCK < pend ? from(pn + BLOCK) : -1;
+        if (n_r >= 0) {
+          n_cell = s.cell[n_r];
+          n_w = s.w[n_r];
+          load_particle<T, D>(s, n_r, n_o, n_u);
+        }
+      } else if (pn + BLOCK < pend) {
+        n_cell = s.cell[pn + BLOCK];
+        n_w = s.w[pn + BLOCK];
+        load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
       }
       const int64_t p = pn;
       int c[3] = {0, 0, 0};
@@ -674,22 +694,22 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-          s.off_o[d][p] = on[d];
+          off_o[d][p] = on[d];
         }
-        s.cell_o[p] = pack(c, g);
-        s.u_o[0][p] = u[0];
-        s.u_o[1][p] = u[1];
-        s.u_o[2][p] = u[2];
-        if (s.open && (c[0] < s.xlo || c[0] >= s.xhi)) s.w_o[p] = T(0);  // removed at an open face
-        else if (s.src) s.w_o[p] = w;
-      } else if (have && s.src) {  // a straggler or a removed particle moves unchanged
+        cell_o[p] = pack(c, g);
+        u_o[0][p] = u[0];
+        u_o[1][p] = u[1];
+        u_o[2][p] = u[2];
+        if (s.open && (c[0] < s.xlo || c[0] >= s.xhi)) w_o[p] = T(0);  // removed at an open face
+        else if (FOLD) w_o[p] = w;
+      } else if (FOLD && have) {  // a straggler or a removed particle moves unchanged
 #pragma unroll
-        for (int d = 0; d < D; ++d) s.off_o[d][p] = o[d];
-        s.cell_o[p] = p_cell;
-        s.u_o[0][p] = u[0];
-        s.u_o[1][p] = u[1];
-        s.u_o[2][p] = u[2];
-        s.w_o[p] = w;
+        for (int d = 0; d < D; ++d) off_o[d][p] = o[d];
+        cell_o[p] = p_cell;
+        u_o[0][p] = u[0];
+        u_o[1][p] = u[1];
+        u_o[2][p] = u[2];
+        w_o[p] = w;
       }
     }
     __syncthreads();
@@ -888,7 +908,9 @@ hipError_t deposit_impl(const pic_ctx &c, const pic_species &sp, const pic_field
 template <typename T, int D, int M, class G, int BLOCK, typename TJ>
 hipError_t launch_tiled_acc(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                             hipStream_t st) {
-  const auto kern = k_push_deposit_tiled<T, D, M, G, BLOCK, TJ>;
+  // only 3D launches fold a sort's copy
+  const auto kern = (D == 3 && sa.src) ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3>
+                                       : k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, false>;
   const size_t lds = c.lds_bytes;
   // granted on every launch (idempotent, and valid for whichever device is current)
   if (lds > 65536) {
@@ -926,6 +948,7 @@ hipError_t launch_tiled(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fi
 template <typename T, int D, int M>
 hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t st, const int32_t *src) {
   if (sp.np == 0) return hipSuccess;
+  if (D != 3 && src) return hipErrorInvalidValue;  // only 3D launches fold a sort's copy
   SpeciesArgs<T> sa = species_args<T>(c, sp);
   if (src) {  // read through the sort's slots, write the second set
     sa.src = src;
