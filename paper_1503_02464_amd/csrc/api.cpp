@@ -421,7 +421,10 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
       }
       PhaseTimer t(c, s, pic::kPhasePush);
       e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s, src);
-      if (e != hipSuccess) return hip_fail(c, e, "push_deposit");
+      if (e != hipSuccess) {
+        if (src) sp[i].sorted = 0;  // the sort's copy may not have happened: its order is not in the arrays
+        return hip_fail(c, e, "push_deposit");
+      }
     }
     {
       PhaseTimer t(c, s, pic::kPhaseYee);
