@@ -17,8 +17,9 @@ Also printed, in the same JSON line:
   kernel sources differ from the ones they were taken on); binding = the
   same record's SQ counters: the fractions of the kernel's cycles the LDS is
   busy and replaying conflicts, and VALU issue (the kernel is LDS-bound);
-* cpu_baseline: the FP64 CPU oracle, one thread, whole steps of a 64^3 box
-  of the same workload (about 10 s);
+* cpu_baseline: the FP64 CPU oracle on the host: one thread on a 64^3 box
+  and every core (the oracle's all-core timing build) on a 128^3 box of the
+  same workload, with the host's core count and CPU model;
 * fp64: the same step in FP64 (value and roofline);
 * adjoint: forward and backward time of the differentiable 2D rollout;
 * laser_foil: time per step of the two laser-on-foil boxes (FP32).
@@ -298,27 +299,64 @@ def copy_probe(nbytes: int = 1 << 30) -> None:
     log(f"copy probe: {nbytes} bytes read and written per copy")
 
 
+def host_facts() -> dict:
+    """The host's cores (this process's CPU affinity), the thread count the
+    all-core leg uses (OMP_NUM_THREADS when set, at most the affinity) and
+    the CPU model."""
+    aff = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(aff, int(env)) if env.isdigit() and int(env) > 0 else aff
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cores_in_affinity": aff, "omp_num_threads": env or None, "threads_used": threads, "cpu_model": model}
+
+
 def cpu_baseline(w) -> dict:
-    """The FP64 oracle, one thread, whole steps of a 64^3 box of the same workload until about 10 s of CPU
-    time have passed (at most 4 steps)."""
+    """The FP64 CPU oracle on the host cores, two legs, each whole steps of a
+    scaled box of the same workload (same dx, dt, shape, momentum spread):
+    one thread on a 64^3 box (about 10 s), then every core of the all-core
+    timing build (particles in per-thread chunks, Yee serial) on a 128^3 box
+    (about 10 s).  value = the all-core leg."""
     import oracle as O
     from paper_1503_02464_amd import inputs
     from paper_1503_02464_amd.configs import thermal_3d
 
-    ws = thermal_3d(scale=4)
-    g = O.Grid(3, ws.n, ws.dx, ws.dt, ws.order)
-    sp = inputs.uniform_plasma(ws.n, 3, ws.ppc, ws.u_sigma, ws.weight, ws.seed)
-    f = O.new_fields(g)
-    t0 = time.perf_counter()
-    steps, el = 0, 0.0
-    while steps < 4 and el < 10.0:
-        O.step(g, f, [sp])
-        steps += 1
-        el = time.perf_counter() - t0
-    npart = sp["w"].shape[0]
-    return {"value": npart * steps / el, "unit": "particle pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} FP64 steps of {ws.n[0]}^3 cells x {ws.ppc} ppc ({npart} particles), same dx, dt, "
-                      f"shape and momentum spread; {el:.1f} s"}
+    host = host_facts()
+
+    def leg(scale: int, threads: int, budget_s: float) -> dict:
+        ws = thermal_3d(scale=scale)
+        g = O.Grid(3, ws.n, ws.dx, ws.dt, ws.order)
+        sp = inputs.uniform_plasma(ws.n, 3, ws.ppc, ws.u_sigma, ws.weight, ws.seed)
+        f = O.new_fields(g)
+        steps, el = 0, 0.0
+        t0 = time.perf_counter()
+        while steps < 4 and el < budget_s:
+            if threads == 1:
+                O.step(g, f, [sp])
+            else:
+                O.step_threads(g, f, [sp], threads)
+            steps += 1
+            el = time.perf_counter() - t0
+        npart = sp["w"].shape[0]
+        return {"value": npart * steps / el, "threads": threads,
+                "sample": f"{steps} FP64 steps of {ws.n[0]}^3 cells x {ws.ppc} ppc ({npart} particles); {el:.1f} s"}
+
+    one = leg(4, 1, 10.0)
+    log(f"cpu baseline, 1 thread: {one['value']:.3e} pushes/s ({one['sample']})")
+    allc = leg(2, host["threads_used"], 8.0)
+    log(f"cpu baseline, {allc['threads']} threads: {allc['value']:.3e} pushes/s ({allc['sample']})")
+    return {"value": allc["value"], "unit": "particle pushes/s", "cores": allc["threads"], "kind": "oracle",
+            "sample": allc["sample"] + "; the all-core timing build of the oracle (same arithmetic, particle chunks "
+                                       "per thread, Yee serial)",
+            "single_thread": {"value": one["value"], "cores": 1, "sample": one["sample"]},
+            "host": host}
 
 
 def main() -> int:

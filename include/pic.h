@@ -107,8 +107,10 @@ typedef struct {
      * 377) and y, z stay periodic; a particle whose x cell leaves
      * [absorb, n[0] - absorb) after a move deposits that move's current and
      * is then removed: its weight becomes 0, the fused step skips it, and
-     * the next sort moves it behind every tile (tile_start[ntiles] is then the
-     * live count).  Weight-0 particles are always inert when open_x = 1. */
+     * the next sort moves it behind every tile and drops it: pic_sort and
+     * pic_step then set the species' np to tile_start[ntiles], the live count
+     * (reading it back synchronises the stream once per sort).  Weight-0
+     * particles are always inert when open_x = 1. */
     int32_t open_x;
     int32_t absorb;        /* cells between each x face and the particle region, >= 2 shape_order + 2,
                               and n[0] >= 2 absorb + 2 (open_x only) */
@@ -219,7 +221,9 @@ pic_status pic_laser_current(pic_ctx *ctx, pic_fields *f, double t, void *stream
 
 /* Bin one species by tile (counting sort by tile index, x-fastest tile
  * numbering); order inside a tile is unspecified.  Writes tile_start, swaps
- * the array sets (see pic_species) and sets sorted = 1. */
+ * the array sets (see pic_species) and sets sorted = 1.  With open_x it also
+ * drops the removed particles (np becomes tile_start[ntiles]) and then
+ * synchronises the stream. */
 pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
 
 /* nsteps whole steps for nspecies species: clear J (and add the laser sheet
@@ -243,6 +247,19 @@ pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields 
 #define PIC_NDIAG 8
 pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
                            double *out_host, void *stream);
+
+/* The charge density on the nodes, rho(node) = sum over particles of
+ * q w / dV S(x - node) with S the shape of the push (Sec. 2: the densities
+ * that the continuity equation ties to J; the uniform neutralising background
+ * is not included), accumulated in FP64 into the caller's device array rho of
+ * n[0]*n[1]*n[2] doubles (node (i,j,k) at i + n0 (j + n1 k)), which it
+ * overwrites.  When gauss is not null it also receives, per node, the
+ * residual of Gauss's law div E - rho with the backward-difference
+ * divergence from the E points onto the nodes (f must then be valid).  Needs
+ * no workspace; enqueues on the stream without synchronising.  PIC_EINVAL for
+ * a null rho, bad species, or gauss without fields. */
+pic_status pic_charge_density(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
+                              double *rho, double *gauss, void *stream);
 
 /* ---- Reverse mode (adjoint) of one step, for gradients of a loss of the
  * final fields through K steps (the discrete adjoint of steps 1-4 above).

@@ -45,6 +45,22 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+_OMP_SRC = os.path.join(_HERE, "oracle_omp.c")
+_OMP_LIB = os.path.join(_HERE, "liboracle_omp.so")
+_omp_lib = None
+
+
+def build_timing(force: bool = False) -> str:
+    """Compile the all-core timing build (oracle_omp.c, which includes oracle.c
+    unchanged) with OpenMP; used only to time the oracle on every host core."""
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_OMP_SRC))
+    if force or not os.path.exists(_OMP_LIB) or os.path.getmtime(_OMP_LIB) < newest:
+        tmp = _OMP_LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *CFLAGS, "-fopenmp", "-o", tmp, _OMP_SRC, "-lm"])
+        os.replace(tmp, _OMP_LIB)
+    return _OMP_LIB
+
+
 class _Grid(ctypes.Structure):
     _fields_ = [
         ("dims", ctypes.c_int32),
@@ -238,6 +254,39 @@ def push_deposit(grid: Grid, fields: dict, sp: dict) -> int:
                               _d(B[0]), _d(B[1]), _d(B[2]), _i(c[0]), _i(c[1]), _i(c[2]), _d(o[0]), _d(o[1]),
                               _d(o[2]), _d(u[0]), _d(u[1]), _d(u[2]), _d(w), _d(J[0]), _d(J[1]), _d(J[2]))
     return int(bad)
+
+
+def push_deposit_threads(grid: Grid, fields: dict, sp: dict, threads: int) -> int:
+    """push_deposit on `threads` OpenMP threads (the all-core timing build):
+    contiguous particle chunks per thread, private current grids added in thread
+    order.  For timing the oracle on every host core, not for parity."""
+    global _omp_lib
+    with _lock:
+        if _omp_lib is None:
+            _omp_lib = _bind(build_timing())
+            _omp_lib.or_push_deposit_omp.argtypes = _omp_lib.or_push_deposit.argtypes + [ctypes.c_int32]
+            _omp_lib.or_push_deposit_omp.restype = ctypes.c_int64
+    E, B, J = fields["E"], fields["B"], fields["J"]
+    c, o, u, w = sp["cell"], sp["off"], sp["u"], sp["w"]
+    g = grid.c()
+    bad = _omp_lib.or_push_deposit_omp(ctypes.byref(g), sp["q"], sp["m"], c.shape[1], _d(E[0]), _d(E[1]), _d(E[2]),
+                                       _d(B[0]), _d(B[1]), _d(B[2]), _i(c[0]), _i(c[1]), _i(c[2]), _d(o[0]),
+                                       _d(o[1]), _d(o[2]), _d(u[0]), _d(u[1]), _d(u[2]), _d(w), _d(J[0]), _d(J[1]),
+                                       _d(J[2]), int(threads))
+    if bad < 0:
+        raise MemoryError("oracle timing build: no memory for the per-thread current grids")
+    return int(bad)
+
+
+def step_threads(grid: Grid, fields: dict, species: list, threads: int) -> int:
+    """step() with the particles on `threads` threads (Yee stays serial: it is
+    under one percent of the oracle's step)."""
+    fields["J"][...] = 0.0
+    bad = 0
+    for sp in species:
+        bad += push_deposit_threads(grid, fields, sp, threads)
+    yee_step(grid, fields)
+    return bad
 
 
 def yee_b(grid: Grid, f: float, E: np.ndarray, B: np.ndarray) -> None:

@@ -120,6 +120,8 @@ def load(path: str = LIB_PATH):
         "pic_sort": (st, [ctx, P(Species), ctypes.c_void_p]),
         "pic_step": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), ctypes.c_int32, ctypes.c_void_p]),
         "pic_diagnostics": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), P(ctypes.c_double), ctypes.c_void_p]),
+        "pic_charge_density": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
         "pic_check": (st, [ctx, ctypes.c_void_p]),
         "pic_set_timing": (st, [ctx, ctypes.c_int32]),
         "pic_get_timing": (st, [ctx, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]),

@@ -464,6 +464,18 @@ pic_status pic_diagnostics(pic_ctx *c, const pic_species *sp, int32_t nspecies, 
   return pic_check(c, stream);
 }
 
+pic_status pic_charge_density(pic_ctx *c, const pic_species *sp, int32_t nspecies, const pic_fields *f, double *rho,
+                              double *gauss, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!rho || nspecies < 0 || (nspecies > 0 && !sp)) return fail(c, PIC_EINVAL, "bad charge density arguments");
+  if (gauss && !fields_ok(f)) return fail(c, PIC_EINVAL, "div E - rho needs the fields");
+  for (int i = 0; i < nspecies; ++i)
+    if (!species_ok(c, &sp[i], false)) return fail(c, PIC_EINVAL, "bad species");
+  hipError_t e = pic::launch_charge_density(*c, sp, nspecies, f, rho, gauss, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "charge_density");
+  return PIC_OK;
+}
+
 pic_status pic_energy_adjoint(pic_ctx *c, const pic_fields *f, pic_fields *lam, double scale, void *stream) {
   if (!c) return PIC_EINVAL;
   if (c->p.open_x) return fail(c, PIC_EINVAL, "the adjoint covers periodic boxes only");

@@ -190,11 +190,12 @@ __global__ void __launch_bounds__(256) k_rho_tiled(const int32_t *cell, const T 
 
 // Slots 4..7 per node: |rho|, |div E - rho|, |G - G_prev|, |(rho - rho_prev)/dt + div J|;
 // then the current rho and G become the previous ones.
+// history = 0: rho_prev and g_prev are neither read nor written (may be null).
 template <typename T, int D>
 __global__ void __launch_bounds__(kB) k_gauss(const T *ex, const T *ey, const T *ez, const T *jx, const T *jy,
                                               const T *jz, const double *rho, double *rho_prev, double *g_prev,
                                               int n0, int n1, int n2, double idx, double idy, double idz, double idt,
-                                              int have_prev, int have_cont, double *partials) {
+                                              int history, int have_prev, int have_cont, double *partials) {
   __shared__ double sh[16];
   const int64_t n = (int64_t)n0 * n1 * n2;
   double mr = 0.0, mg = 0.0, mdg = 0.0, mc = 0.0;
@@ -215,10 +216,12 @@ __global__ void __launch_bounds__(kB) k_gauss(const T *ex, const T *ey, const T 
     const double g = dE - r;
     mr = fmax(mr, fabs(r));
     mg = fmax(mg, fabs(g));
-    if (have_prev) mdg = fmax(mdg, fabs(g - g_prev[o]));
-    if (have_cont) mc = fmax(mc, fabs((r - rho_prev[o]) * idt + dJ));
-    rho_prev[o] = r;
-    g_prev[o] = g;
+    if (history) {
+      if (have_prev) mdg = fmax(mdg, fabs(g - g_prev[o]));
+      if (have_cont) mc = fmax(mc, fabs((r - rho_prev[o]) * idt + dJ));
+      rho_prev[o] = r;
+      g_prev[o] = g;
+    }
   }
   mr = block_max(mr, sh);
   mg = block_max(mg, sh);
@@ -229,6 +232,25 @@ __global__ void __launch_bounds__(kB) k_gauss(const T *ex, const T *ey, const T 
     partials[5 * kStride + blockIdx.x] = mg;
     partials[6 * kStride + blockIdx.x] = mdg;
     partials[7 * kStride + blockIdx.x] = mc;
+  }
+}
+
+// G = div E - rho per node (the uniform background excluded), backward
+// differences from the E points onto the nodes.
+template <typename T, int D>
+__global__ void __launch_bounds__(kB) k_gauss_grid(const T *ex, const T *ey, const T *ez, const double *rho, int n0,
+                                                   int n1, int n2, double idx, double idy, double idz, double *out) {
+  const int64_t n = (int64_t)n0 * n1 * n2;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n; o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = static_cast<int>(o % n0);
+    const int j = static_cast<int>((o / n0) % n1);
+    const int k = static_cast<int>(o / ((int64_t)n0 * n1));
+    const int64_t im = i == 0 ? o + (n0 - 1) : o - 1;
+    const int64_t jm = j == 0 ? o + (int64_t)n0 * (n1 - 1) : o - n0;
+    const int64_t km = k == 0 ? o + (int64_t)n0 * n1 * (n2 - 1) : o - (int64_t)n0 * n1;
+    double dE = (static_cast<double>(ex[o]) - ex[im]) * idx + (static_cast<double>(ey[o]) - ey[jm]) * idy;
+    if (D == 3) dE += (static_cast<double>(ez[o]) - ez[km]) * idz;
+    out[o] = dE - rho[o];
   }
 }
 
@@ -250,32 +272,30 @@ __global__ void __launch_bounds__(1024) k_final(const double *partials, int cnt_
   }
 }
 
+// Where one diagnostics pass keeps its partial sums, charge grid and result,
+// and whether it reads and renews the previous call's rho and G.
+struct DiagBufs {
+  double *partials;  // [kDiagSlots][kStride]
+  double *rho;       // [ncells]
+  double *rho_prev;  // [ncells] (history only)
+  double *g_prev;    // [ncells] (history only)
+  double *result;    // [kDiagSlots]
+  bool history, have_prev, have_cont;
+};
+
+// rho(node) = sum over the species' particles of q w / dV S(x - node), into
+// rho (cleared first): per tile in LDS for sorted species whose tile box
+// fits, else one thread per particle with HBM atomics.
 template <typename T, int D, int M>
-hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_fields &f, bool have_prev, bool have_cont,
-               hipStream_t s) {
-  double *partials = c.wsp<double>(c.ws.partials);
-  double *rho = c.wsp<double>(c.ws.rho);
+hipError_t charge_grid(const pic_ctx &c, const pic_species *sp, int nsp, double *rho, hipStream_t s) {
   const int64_t n = c.ncells;
   double dV = 1.0;
   for (int d = 0; d < c.p.dims; ++d) dV *= c.p.dx[d];
-  int gblocks = static_cast<int>((n + kB - 1) / kB);
-  if (gblocks > kDiagBlocks) gblocks = kDiagBlocks;
-  hipLaunchKernelGGL(k_field_sq<T>, dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
-                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.B[0]),
-                     static_cast<const T *>(f.B[1]), static_cast<const T *>(f.B[2]), n, partials);
   hipError_t e = launch_fill_zero(rho, n, 8, s);
-  if (e != hipSuccess) return e;
-  // clear the particle slots (species that are empty leave their blocks unused)
-  e = launch_fill_zero(partials + 2 * kStride, 2 * kStride, 8, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < nsp; ++i) {
     const pic_species &q = sp[i];
     if (q.np == 0) continue;
-    int pb = static_cast<int>((q.np + kB - 1) / kB);
-    if (pb > kDiagBlocks) pb = kDiagBlocks;
-    hipLaunchKernelGGL(k_particle_sums<T>, dim3(pb), dim3(kB), 0, s, static_cast<const T *>(q.u[0]),
-                       static_cast<const T *>(q.u[1]), static_cast<const T *>(q.u[2]), static_cast<const T *>(q.w),
-                       q.np, q.q, q.m, partials, i * kDiagBlocks);
     if (q.sorted && q.tile_start) {
       const int sl = c.p.slack;
       size_t box = static_cast<size_t>(c.p.tile[0] + 2 * sl + 3) * (c.p.tile[1] + 2 * sl + 3) *
@@ -297,34 +317,89 @@ hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_field
                        (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1, static_cast<int>(c.n[0]),
                        static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), rho);
   }
-  hipLaunchKernelGGL((k_gauss<T, D>), dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
-                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.J[0]),
-                     static_cast<const T *>(f.J[1]), static_cast<const T *>(f.J[2]), rho,
-                     c.wsp<double>(c.ws.rho_prev), c.wsp<double>(c.ws.gauss_prev), static_cast<int>(c.n[0]),
-                     static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), 1.0 / c.p.dx[0], 1.0 / c.p.dx[1],
-                     c.p.dims == 3 ? 1.0 / c.p.dx[2] : 0.0, 1.0 / c.p.dt, have_prev ? 1 : 0, have_cont ? 1 : 0,
-                     partials);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, partials, gblocks, kMaxSpecies * kDiagBlocks, gblocks, dV,
-                     c.wsp<double>(c.ws.result));
   return hipGetLastError();
 }
+
+int grid_blocks(const pic_ctx &c) {
+  int gblocks = static_cast<int>((c.ncells + kB - 1) / kB);
+  return gblocks > kDiagBlocks ? kDiagBlocks : gblocks;
+}
+
+template <typename T, int D, int M>
+hipError_t run(const pic_ctx &c, const pic_species *sp, int nsp, const pic_fields &f, const DiagBufs &b,
+               hipStream_t s) {
+  const int64_t n = c.ncells;
+  double dV = 1.0;
+  for (int d = 0; d < c.p.dims; ++d) dV *= c.p.dx[d];
+  const int gblocks = grid_blocks(c);
+  hipLaunchKernelGGL(k_field_sq<T>, dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
+                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.B[0]),
+                     static_cast<const T *>(f.B[1]), static_cast<const T *>(f.B[2]), n, b.partials);
+  // clear the particle slots (species that are empty leave their blocks unused)
+  hipError_t e = launch_fill_zero(b.partials + 2 * kStride, 2 * kStride, 8, s);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < nsp; ++i) {
+    const pic_species &q = sp[i];
+    if (q.np == 0) continue;
+    int pb = static_cast<int>((q.np + kB - 1) / kB);
+    if (pb > kDiagBlocks) pb = kDiagBlocks;
+    hipLaunchKernelGGL(k_particle_sums<T>, dim3(pb), dim3(kB), 0, s, static_cast<const T *>(q.u[0]),
+                       static_cast<const T *>(q.u[1]), static_cast<const T *>(q.u[2]), static_cast<const T *>(q.w),
+                       q.np, q.q, q.m, b.partials, i * kDiagBlocks);
+  }
+  e = charge_grid<T, D, M>(c, sp, nsp, b.rho, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gauss<T, D>), dim3(gblocks), dim3(kB), 0, s, static_cast<const T *>(f.E[0]),
+                     static_cast<const T *>(f.E[1]), static_cast<const T *>(f.E[2]), static_cast<const T *>(f.J[0]),
+                     static_cast<const T *>(f.J[1]), static_cast<const T *>(f.J[2]), b.rho, b.rho_prev, b.g_prev,
+                     static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), 1.0 / c.p.dx[0],
+                     1.0 / c.p.dx[1], c.p.dims == 3 ? 1.0 / c.p.dx[2] : 0.0, 1.0 / c.p.dt, b.history ? 1 : 0,
+                     b.have_prev ? 1 : 0, b.have_cont ? 1 : 0, b.partials);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(1024), 0, s, b.partials, gblocks, kMaxSpecies * kDiagBlocks, gblocks, dV,
+                     b.result);
+  return hipGetLastError();
+}
+
+template <typename T, int D, int M>
+hipError_t density(const pic_ctx &c, const pic_species *sp, int nsp, const pic_fields *f, double *rho, double *gauss,
+                   hipStream_t s) {
+  hipError_t e = charge_grid<T, D, M>(c, sp, nsp, rho, s);
+  if (e != hipSuccess || !gauss) return e;
+  hipLaunchKernelGGL((k_gauss_grid<T, D>), dim3(grid_blocks(c)), dim3(kB), 0, s, static_cast<const T *>(f->E[0]),
+                     static_cast<const T *>(f->E[1]), static_cast<const T *>(f->E[2]), rho, static_cast<int>(c.n[0]),
+                     static_cast<int>(c.n[1]), static_cast<int>(c.n[2]), 1.0 / c.p.dx[0], 1.0 / c.p.dx[1],
+                     c.p.dims == 3 ? 1.0 / c.p.dx[2] : 0.0, gauss);
+  return hipGetLastError();
+}
+
+#define PIC_DIAG_DISPATCH(F, ...)                                                     \
+  do {                                                                                \
+    const bool f64 = c.p.precision == PIC_FP64;                                       \
+    const int key = (f64 ? 4 : 0) + (c.p.dims == 3 ? 2 : 0) + (c.p.shape_order - 1); \
+    switch (key) {                                                                    \
+      case 0: return F<float, 2, 1>(__VA_ARGS__);                                    \
+      case 1: return F<float, 2, 2>(__VA_ARGS__);                                    \
+      case 2: return F<float, 3, 1>(__VA_ARGS__);                                    \
+      case 3: return F<float, 3, 2>(__VA_ARGS__);                                    \
+      case 4: return F<double, 2, 1>(__VA_ARGS__);                                   \
+      case 5: return F<double, 2, 2>(__VA_ARGS__);                                   \
+      case 6: return F<double, 3, 1>(__VA_ARGS__);                                   \
+      default: return F<double, 3, 2>(__VA_ARGS__);                                  \
+    }                                                                                 \
+  } while (0)
 
 }  // namespace
 
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
                               bool have_prev, bool have_cont, hipStream_t s) {
-  const bool f64 = c.p.precision == PIC_FP64;
-  const int key = (f64 ? 4 : 0) + (c.p.dims == 3 ? 2 : 0) + (c.p.shape_order - 1);
-  switch (key) {
-    case 0: return run<float, 2, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 1: return run<float, 2, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 2: return run<float, 3, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 3: return run<float, 3, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 4: return run<double, 2, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 5: return run<double, 2, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
-    case 6: return run<double, 3, 1>(c, sp, nspecies, f, have_prev, have_cont, s);
-    default: return run<double, 3, 2>(c, sp, nspecies, f, have_prev, have_cont, s);
-  }
+  DiagBufs b{c.wsp<double>(c.ws.partials), c.wsp<double>(c.ws.rho), c.wsp<double>(c.ws.rho_prev),
+             c.wsp<double>(c.ws.gauss_prev), c.wsp<double>(c.ws.result), true, have_prev, have_cont};
+  PIC_DIAG_DISPATCH(run, c, sp, nspecies, f, b, s);
+}
+
+hipError_t launch_charge_density(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields *f,
+                                 double *rho, double *gauss, hipStream_t s) {
+  PIC_DIAG_DISPATCH(density, c, sp, nspecies, f, rho, gauss, s);
 }
 
 }  // namespace pic

@@ -151,5 +151,9 @@ int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
                               bool have_prev, bool have_cont, hipStream_t s);
+// rho (and, when gauss is not null, div E - rho) into caller-owned FP64 grids.
+hipError_t launch_charge_density(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields *f,
+                                 double *rho, double *gauss, hipStream_t s);
+
 
 }  // namespace pic

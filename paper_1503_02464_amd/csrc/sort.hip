@@ -698,6 +698,16 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
     *fold_src = c.wsp<int32_t>(c.ws.sort_src);  // the caller's push copies, then swaps
   }
   sp.sorted = 1;
+  if (c.p.open_x && sp.np > 0) {
+    // The removed particles now sit behind every tile, from tile_start[ntiles]
+    // on: the species keeps only the live ones (a folded copy then never
+    // reads the removed ones, and later sorts never rank them).
+    int32_t nlive = 0;
+    e = hipMemcpyAsync(&nlive, sp.tile_start + c.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (nlive >= 0 && nlive < sp.np) sp.np = nlive;
+  }
   c.sorted_runs[slot].second = sp.np;
   return hipSuccess;
 }

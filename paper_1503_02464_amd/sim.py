@@ -259,17 +259,23 @@ class Simulation:
         return s.current()["w"][:s.np] != 0
 
     def sort(self, s: SpeciesState) -> None:
-        self._call(self.lib.pic_sort(self.ctx, ctypes.byref(s.struct), ctypes.c_void_p(_stream())), "pic_sort")
+        try:
+            self._call(self.lib.pic_sort(self.ctx, ctypes.byref(s.struct), ctypes.c_void_p(_stream())), "pic_sort")
+        finally:  # with open x faces the sort drops the removed particles
+            s.np = int(s.struct.np)
 
     def step(self, nsteps: int = 1, species: list | None = None) -> None:
         sp = species if species is not None else self.species
         arr = (L.Species * max(len(sp), 1))()
         for i, s in enumerate(sp):
             arr[i] = s.struct
-        self._call(self.lib.pic_step(self.ctx, arr, len(sp), ctypes.byref(self.fstruct), int(nsteps),
-                                     ctypes.c_void_p(_stream())), "pic_step")
-        for i, s in enumerate(sp):
-            s.struct = arr[i]
+        try:
+            self._call(self.lib.pic_step(self.ctx, arr, len(sp), ctypes.byref(self.fstruct), int(nsteps),
+                                         ctypes.c_void_p(_stream())), "pic_step")
+        finally:  # also after a failure: the library may have swapped sets, dropped removed
+            for i, s in enumerate(sp):  # particles or cleared sorted
+                s.struct = arr[i]
+                s.np = int(arr[i].np)
 
     def diagnostics(self, species: list | None = None) -> dict:
         sp = species if species is not None else self.species
@@ -281,6 +287,22 @@ class Simulation:
                                             ctypes.c_void_p(_stream())), "pic_diagnostics")
         keys = ("UE", "UB", "K", "Q", "rho_max", "gauss_max", "gauss_change", "continuity")
         return dict(zip(keys, list(out)))
+
+    def charge_density(self, species: list | None = None, gauss: bool = False):
+        """The FP64 charge density on the nodes (and div E - rho when gauss),
+        computed by the library into device grids; returns numpy arrays."""
+        sp = species if species is not None else self.species
+        arr = (L.Species * max(len(sp), 1))()
+        for i, s in enumerate(sp):
+            arr[i] = s.struct
+        rho = torch.empty(self.ncells, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.ncells, dtype=torch.float64, device=self.device) if gauss else None
+        self._call(self.lib.pic_charge_density(self.ctx, arr, len(sp), ctypes.byref(self.fstruct),
+                                               ctypes.c_void_p(_ptr(rho)),
+                                               ctypes.c_void_p(_ptr(g) if g is not None else None),
+                                               ctypes.c_void_p(_stream())), "pic_charge_density")
+        torch.cuda.synchronize()
+        return (rho.cpu().numpy(), g.cpu().numpy()) if gauss else rho.cpu().numpy()
 
     def check(self) -> None:
         self._call(self.lib.pic_check(self.ctx, ctypes.c_void_p(_stream())), "pic_check")

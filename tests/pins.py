@@ -679,6 +679,75 @@ def pin_absorption_gauss():
         sp = out[0]
 
 
+# ------------------------------------------------------------------ diagnostics
+
+def pin_field_energy_uniform(dims=3):
+    """A uniform field F0 on an anisotropic box: 1/2 sum |F|^2 dV = 1/2 |F0|^2 N dV
+    exactly (every cell holds the same value)."""
+    g = grid(dims, (6, 5, 4)[:dims], dx=(0.1, 0.07, 0.12), cfl=0.6)
+    dV = g.dx[0] * g.dx[1] * (g.dx[2] if dims == 3 else 1.0)
+    F0 = np.array([0.75, -1.5, 2.25])
+    F = np.repeat(F0[:, None], g.ncells, axis=1)
+    want = 0.5 * float(F0 @ F0) * g.ncells * dV
+    got = O.field_energy(g, F)
+    assert abs(got - want) <= 1e-14 * want, (got, want)
+
+
+def pin_field_energy_plane_wave(dims=3):
+    """A lattice plane wave F = Fhat cos(k.x) with k a non-zero, non-Nyquist
+    grid wavenumber: the sum of cos^2 over whole periods is N/2, so the energy is
+    1/4 |Fhat|^2 V (V the box volume)."""
+    g = grid(dims, (8, 6, 10)[:dims], dx=(0.1, 0.07, 0.12), cfl=0.6)
+    m = (1, 2, 3)
+    o = np.arange(g.ncells)
+    ijk = (o % g.n[0], (o // g.n[0]) % g.n[1], o // (g.n[0] * g.n[1]))  # x fastest
+    phase = sum(2 * np.pi * m[d] * ijk[d] / g.n[d] for d in range(dims)) + 0.3
+    Fhat = np.array([0.5, -0.25, 1.25])
+    F = Fhat[:, None] * np.cos(phase)[None, :]
+    V = g.ncells * g.dx[0] * g.dx[1] * (g.dx[2] if dims == 3 else 1.0)
+    want = 0.25 * float(Fhat @ Fhat) * V
+    got = O.field_energy(g, F)
+    assert abs(got - want) <= 1e-13 * want, (got, want)
+
+
+def pin_kinetic_energy_rational():
+    """Momenta with rational gamma: |u| = 3/4 gives gamma - 1 = 1/4 and
+    |u| = 4/3 gives gamma - 1 = 2/3; a particle at rest adds nothing and a slow
+    one adds 1/2 m w u^2 (to relative order u^2).  K = sum w m (gamma - 1) for an
+    electron (m = 1) and a proton (m = 1836)."""
+    u = np.zeros((3, 4))
+    u[:, 0] = (0.45, 0.6, 0.0)                       # |u| = 3/4
+    u[:, 1] = (0.0, 4.0 / 3.0 * 0.8, 4.0 / 3.0 * 0.6)  # |u| = 4/3
+    u[:, 3] = (1e-4, 0.0, 0.0)                       # slow; particle 2 at rest
+    w = np.array([0.5, 2.0, 3.0, 7.0])
+    for m in (1.0, 1836.0):
+        want = m * (0.5 * 0.25 + 2.0 * (2.0 / 3.0) + 7.0 * 0.5e-8)
+        got = O.kinetic_energy({"m": m, "u": u, "w": w})
+        assert abs(got - want) <= 1e-12 * want, (m, got, want)
+
+
+def pin_tile_sort_hand_counted():
+    """Tile keys (x fastest) and the stable counting sort of a hand-counted
+    case: 2D box 8 x 4 in 4 x 2 tiles, and a 3D box 4 x 4 x 4 in 2 x 2 x 2 tiles."""
+    g2 = grid(2, (8, 4))
+    cell = np.array([[0, 5, 3, 7, 4, 1], [0, 1, 3, 2, 0, 2], [0, 0, 0, 0, 0, 0]], np.int32)
+    assert O.tile_keys(g2, (4, 2, 1), cell).tolist() == [0, 1, 2, 3, 1, 2]
+    sp = {"q": -1.0, "m": 1.0, "cell": cell, "off": np.zeros((3, 6)), "u": np.zeros((3, 6)),
+          "w": np.arange(6, dtype=np.float64)}
+    out, start = O.tile_sort(g2, (4, 2, 1), sp)
+    assert out["w"].tolist() == [0, 1, 4, 2, 5, 3]
+    assert start.tolist() == [0, 1, 3, 5, 6]
+    g3 = grid(3, (4, 4, 4))
+    c3 = np.array([[3, 0, 2, 1], [0, 3, 2, 1], [0, 0, 3, 1]], np.int32)
+    # tiles (1,0,0) -> 1, (0,1,0) -> 2, (1,1,1) -> 7, (0,0,0) -> 0
+    assert O.tile_keys(g3, (2, 2, 2), c3).tolist() == [1, 2, 7, 0]
+    sp3 = {"q": -1.0, "m": 1.0, "cell": c3, "off": np.zeros((3, 4)), "u": np.zeros((3, 4)),
+           "w": np.arange(4, dtype=np.float64)}
+    out3, start3 = O.tile_sort(g3, (2, 2, 2), sp3)
+    assert out3["w"].tolist() == [3, 0, 1, 2]
+    assert start3.tolist() == [0, 1, 2, 3, 3, 3, 3, 3, 4]
+
+
 ALL_PINS = [
     pin_shape_values, pin_shape_moments,
     lambda: pin_gather_uniform(3, 2), lambda: pin_gather_uniform(2, 1),
@@ -698,4 +767,7 @@ ALL_PINS = [
     lambda: pin_translation_invariance(3, 2), lambda: pin_translation_invariance(2, 1),
     lambda: pin_mur_exact_reflection(2), lambda: pin_mur_exact_reflection(3), pin_laser_plane_wave,
     pin_absorption_gauss,
+    lambda: pin_field_energy_uniform(3), lambda: pin_field_energy_uniform(2),
+    lambda: pin_field_energy_plane_wave(3), lambda: pin_field_energy_plane_wave(2),
+    pin_kinetic_energy_rational, pin_tile_sort_hand_counted,
 ]

@@ -222,7 +222,19 @@ def test_diagnostics(prec, dims, order):
     assert abs(d0["rho_max"] - np.max(np.abs(ref["rho"]))) <= tol * np.max(np.abs(ref["rho"]))
     assert abs(d0["gauss_max"] - np.max(np.abs(ref["gauss"]))) <= max(tol, 1e-12) * np.max(np.abs(ref["gauss"]))
     assert np.isnan(d0["gauss_change"]) and np.isnan(d0["continuity"])
+    # the charge density and Gauss's residual node by node (FP64 sums of an
+    # FP32-exact state: round-off only, for both precisions)
+    rho0, g0 = s.charge_density(gauss=True)
+    assert rel(rho0, ref["rho"]) <= 1e-12, rel(rho0, ref["rho"])
+    assert rel(g0, ref["gauss"]) <= 1e-12, rel(g0, ref["gauss"])
     s.step(1)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    rho1, g1 = s.charge_density(gauss=True)
+    tol1 = 1e-12 if prec == "fp64" else 2e-6  # one FP32 step: positions to 4e-7 cells
+    assert rel(rho1, O.rho(g, [ref_sp])) <= tol1, rel(rho1, O.rho(g, [ref_sp]))
+    ref_g1 = O.div(g, ref_f["E"]) - O.rho(g, [ref_sp])
+    assert rel(g1, ref_g1) <= tol1, rel(g1, ref_g1)
     d1 = s.diagnostics()
     # continuity and Gauss's law hold to round-off on the GPU path too
     scale = d1["rho_max"]

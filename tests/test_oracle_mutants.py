@@ -4,6 +4,7 @@ asserts that at least one pin fails against it."""
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -53,6 +54,10 @@ MUTANTS = [
     ("rho_volume", "+= q * w[p] / dV * (wx * wy * wz);", "+= q * w[p] * (wx * wy * wz);"),
     ("div_stagger", "double d = (Fx[o] - Fx[lin(g, i - 1, j, k)]) / g->dx[0]",
      "double d = (Fx[lin(g, i + 1, j, k)] - Fx[o]) / g->dx[0]"),
+    ("field_energy_half", "return 0.5 * s * cell_volume(g);", "return s * cell_volume(g);"),
+    ("field_energy_volume", "return 0.5 * s * cell_volume(g);", "return 0.5 * s;"),
+    ("kinetic_gamma", "s += w[p] * m * (gam - 1.0);", "s += w[p] * m * gam;"),
+    ("kinetic_mass", "s += w[p] * m * (gam - 1.0);", "s += w[p] * (gam - 1.0);"),
 ]
 
 
@@ -80,3 +85,48 @@ def test_pins_catch_mutant(tmp_path, name, old, new):
     with oracle.use_library(str(so)):
         failed = _run_pins()
     assert failed, f"no pin caught mutant {name}"
+
+
+def _keys_y_fastest(grid, tile, cell):
+    nty = grid.n[1] // tile[1]
+    ntx = grid.n[0] // tile[0]
+    tz = cell[2] // tile[2] if grid.dims == 3 else np.zeros_like(cell[0])
+    return (cell[1] // tile[1] + nty * (cell[0] // tile[0] + ntx * tz)).astype(np.int64)
+
+
+def _keys_no_z(grid, tile, cell):
+    ntx = grid.n[0] // tile[0]
+    return (cell[0] // tile[0] + ntx * (cell[1] // tile[1])).astype(np.int64)
+
+
+def _sort_reversed_ties(grid, tile, sp):
+    keys = oracle.tile_keys(grid, tile, sp["cell"])
+    order = np.lexsort((-np.arange(keys.shape[0]), keys))  # equal keys in reverse order
+    out = dict(sp)
+    for k in ("cell", "off", "u"):
+        out[k] = np.ascontiguousarray(sp[k][:, order])
+    out["w"] = np.ascontiguousarray(sp["w"][order])
+    ntiles = (grid.n[0] // tile[0]) * (grid.n[1] // tile[1]) * (grid.n[2] // tile[2])
+    start = np.zeros(ntiles + 1, np.int64)
+    start[1:] = np.cumsum(np.bincount(keys, minlength=ntiles))
+    return out, start
+
+
+def _sort_starts_shifted(grid, tile, sp):
+    out, start = _ORIG_SORT(grid, tile, sp)
+    start = start.copy()
+    start[1:-1] += 1
+    return out, start
+
+
+_ORIG_SORT = oracle.tile_sort
+
+
+@pytest.mark.parametrize("name,attr,fn", [("keys_y_fastest", "tile_keys", _keys_y_fastest),
+                                          ("keys_drop_z", "tile_keys", _keys_no_z),
+                                          ("sort_unstable", "tile_sort", _sort_reversed_ties),
+                                          ("sort_starts", "tile_sort", _sort_starts_shifted)])
+def test_tile_pin_catches_python_mutant(monkeypatch, name, attr, fn):
+    monkeypatch.setattr(oracle, attr, fn)
+    with pytest.raises(AssertionError):
+        pins.pin_tile_sort_hand_counted()

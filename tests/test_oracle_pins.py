@@ -17,6 +17,8 @@ IDS = [
     "cold_k0_2d_l", "cold_k0_3d_q", "plasma_frequency",
     "gauss_3d_q", "gauss_2d_l", "translation_3d_q", "translation_2d_l",
     "mur_reflection_2d", "mur_reflection_3d", "laser_plane_wave", "absorption_gauss",
+    "field_energy_uniform_3d", "field_energy_uniform_2d", "field_energy_wave_3d", "field_energy_wave_2d",
+    "kinetic_energy_rational", "tile_sort_hand_counted",
 ]
 assert len(IDS) == len(pins.ALL_PINS)
 
