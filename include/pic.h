@@ -78,11 +78,20 @@ typedef enum {
 
 enum { PIC_FP32 = 0, PIC_FP64 = 1 };
 
-/* Accumulation type of the on-chip current tile of the fused kernel.  AUTO
- * (the default) is FP64 for both precisions: on gfx950 LDS float atomics in
- * double cost about a third of those in single precision, and the wider
- * accumulator is also more accurate.  FP32 is accepted for an FP32 state. */
-enum { PIC_ACC_AUTO = 0, PIC_ACC_FP32 = 1, PIC_ACC_FP64 = 2 };
+/* Accumulation type of the on-chip current tile of the fused kernel.
+ *   FP64: double LDS atomics.
+ *   FIX64 (FP32 state only): 64-bit fixed point.  Each contribution, bounded
+ *     by |q/dV (dx_d/dt)| w_max (|q|/dA w_max for J_z in 2D) with w_max the
+ *     largest |w| among the tile's particles, is scaled by a power of two so
+ *     that the bound is at most 2^30, rounded to an integer and added with a
+ *     64-bit integer LDS atomic; the merge scales the tile's sums back.  The
+ *     rounding is at most 2^-31 of the bound per contribution, below the FP32
+ *     arithmetic's own.  Integer LDS atomics cost about half as much as double
+ *     ones on gfx950 when lanes collide on banks.
+ *   FP32: single-precision LDS atomics (accepted for an FP32 state; slow on
+ *     gfx950, where the LDS unit serialises them lane by lane).
+ *   AUTO (the default): FIX64 for an FP32 state, FP64 for an FP64 state. */
+enum { PIC_ACC_AUTO = 0, PIC_ACC_FP32 = 1, PIC_ACC_FP64 = 2, PIC_ACC_FIX64 = 3 };
 
 /* The "grid" element of the paper's object model (Sec. 3.2). */
 typedef struct {
@@ -141,11 +150,22 @@ typedef struct {
 } pic_laser;
 
 /* The "em-field" element (Sec. 3.2): E, B and J as nine device arrays of
- * n[0]*n[1]*n[2] float or double values each (layout above). */
+ * n[0]*n[1]*n[2] float or double values each (layout above).
+ *
+ * E_alt and B_alt: an optional second set of E and B arrays of the same
+ * sizes (all six set, or all null).  With them, in 3D boxes whose n[0] is a
+ * multiple of 64 and n[1] a multiple of 8, pic_step and pic_yee_step advance
+ * the fields in one pass that reads E^n, B^n, J and writes E^{n+1}, B^{n+1}
+ * into the second set, then swap the two sets in this struct (after the
+ * call E, B name what were E_alt, B_alt).  Without them, or in other boxes,
+ * the Yee step runs in place in three passes.  The other calls read E and
+ * B only. */
 typedef struct {
     void *E[3];
     void *B[3];
     void *J[3];
+    void *E_alt[3];
+    void *B_alt[3];
 } pic_fields;
 
 /* The "particle" element (Sec. 3.2) for one species (charge q, mass m). */

@@ -13,7 +13,7 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "pic.h")
 
 PIC_OK, PIC_EINVAL, PIC_ECFL, PIC_EHIP, PIC_ENOMEM, PIC_ECROSS, PIC_ENAN, PIC_ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 PIC_FP32, PIC_FP64 = 0, 1
-PIC_ACC_AUTO, PIC_ACC_FP32, PIC_ACC_FP64 = 0, 1, 2
+PIC_ACC_AUTO, PIC_ACC_FP32, PIC_ACC_FP64, PIC_ACC_FIX64 = 0, 1, 2, 3
 PIC_NDIAG = 8
 PIC_NPHASE = 4
 PHASES = ("sort", "zero_current", "push_deposit", "yee")
@@ -57,7 +57,7 @@ class Laser(ctypes.Structure):
 
 
 class Fields(ctypes.Structure):
-    _fields_ = [("E", _c3p), ("B", _c3p), ("J", _c3p)]
+    _fields_ = [("E", _c3p), ("B", _c3p), ("J", _c3p), ("E_alt", _c3p), ("B_alt", _c3p)]
 
 
 class Species(ctypes.Structure):

@@ -1,4 +1,4 @@
-"""The five synthetic workloads, in normalised units (c = eps0 = 1, charge in e,
+"""The synthetic workloads, in normalised units (c = eps0 = 1, charge in e,
 mass in m_e, lengths in c/omega_p for plasma boxes, c/omega_L for laser boxes).
 
 Readings where the workload text is silent (each is listed with its reason in
@@ -183,8 +183,22 @@ def laser_foil_3d(scale: int = 1) -> LaserFoil:
                      10 * lam, tile=(8, 8, 8), seed=1003, sort_levels=32)
 
 
+def two_stream_3d(scale: int = 1) -> Workload:
+    """The paper's scaling workload (Sec. 4): two counter-streaming beams filling
+    a periodic 512x512x128 box (divided by ``scale`` per dimension), 54
+    particles per cell.  Readings where the paper is silent: electrons only
+    over a fixed neutralising background, 27 particles per cell per beam at
+    uniform random offsets, beam momenta +-0.1 m_e c along x with a spread of
+    0.001 m_e c, density 1 (0.5 per beam), dx = 0.05 c/omega_p (the most
+    unstable wavelength, about 1 c/omega_p, spans 20 cells), dt = 0.7 of the Yee
+    limit, quadratic shape, FP32."""
+    n = (512 // scale, 512 // scale, 128 // scale)
+    return Workload(f"two-stream-3d3v-{n[0]}x{n[1]}x{n[2]}-54ppc-quadratic", 3, n, (0.05, 0.05, 0.05), 0.7, 2, 54,
+                    0.001, 200, seed=1005, tile=(8, 8, 8), extra={"u0": 0.1, "beams": 2, "sort_levels": 64})
+
+
 WORKLOADS = {"uniform-2d-64": uniform_2d_small, "laser-foil-2d": laser_foil_2d, "thermal-3d-256": thermal_3d,
-             "laser-foil-3d": laser_foil_3d, "diff-2d-512": diff_2d}
+             "laser-foil-3d": laser_foil_3d, "diff-2d-512": diff_2d, "two-stream-3d": two_stream_3d}
 
 
 # Launch configuration of the fused step for the 3D benchmark workload, per

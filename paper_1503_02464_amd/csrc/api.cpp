@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "pic_internal.h"
 
@@ -110,8 +111,19 @@ void collect_timing(pic_ctx *c) {
   c->events.clear();
 }
 
-// B half step, E step (with the Mur faces when open_x), B half step.
-hipError_t yee_step(pic_ctx *c, const pic_fields &f, hipStream_t s) {
+// B half step, E step (with the Mur faces when open_x), B half step: in one
+// pass into the second field set, which then becomes the current one, when
+// the caller gave one and the box suits; else in place in three passes.
+hipError_t yee_step(pic_ctx *c, pic_fields &f, hipStream_t s) {
+  if (pic::yee_fused_ok(*c, f)) {
+    hipError_t e = pic::launch_yee_fused(*c, f, s);
+    if (e != hipSuccess) return e;
+    for (int d = 0; d < 3; ++d) {
+      std::swap(f.E[d], f.E_alt[d]);
+      std::swap(f.B[d], f.B_alt[d]);
+    }
+    return hipSuccess;
+  }
   hipError_t e = pic::launch_yee_b(*c, f, 0.5, s);
   if (e == hipSuccess && c->p.open_x) e = pic::launch_mur(*c, f, true, s);
   if (e == hipSuccess) e = pic::launch_yee_e(*c, f, s);
@@ -151,9 +163,11 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   if (p->precision != PIC_FP32 && p->precision != PIC_FP64) return PIC_EINVAL;
   if (p->max_particles < 0 || p->max_particles > (int64_t(1) << 31) - 1) return PIC_EINVAL;
   if (p->sort_every < 0 || p->slack < 0 || p->slack > 4) return PIC_EINVAL;
-  if (p->current_accum != PIC_ACC_AUTO && p->current_accum != PIC_ACC_FP32 && p->current_accum != PIC_ACC_FP64)
+  if (p->current_accum != PIC_ACC_AUTO && p->current_accum != PIC_ACC_FP32 && p->current_accum != PIC_ACC_FP64 &&
+      p->current_accum != PIC_ACC_FIX64)
     return PIC_EINVAL;
-  if (p->precision == PIC_FP64 && p->current_accum == PIC_ACC_FP32) return PIC_EINVAL;
+  if (p->precision == PIC_FP64 && (p->current_accum == PIC_ACC_FP32 || p->current_accum == PIC_ACC_FIX64))
+    return PIC_EINVAL;
   if (p->open_x != 0 && p->open_x != 1) return PIC_EINVAL;
   if (p->sort_levels != 0 && (p->sort_levels < 2 || p->sort_levels > pic::kMaxSortLevels)) return PIC_EINVAL;
   if (p->open_x && (p->absorb < 2 * p->shape_order + 2 || p->n[0] < 2 * static_cast<int64_t>(p->absorb) + 2))
@@ -194,6 +208,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   c->elem = p->precision == PIC_FP64 ? 8 : 4;
   c->levels = p->sort_levels ? p->sort_levels : 32;
   c->acc64 = p->current_accum != PIC_ACC_FP32;
+  c->accfix = p->precision == PIC_FP32 && (p->current_accum == PIC_ACC_FIX64 || p->current_accum == PIC_ACC_AUTO);
   const size_t jelem = c->acc64 ? 8 : 4;
   // LDS tile geometry: the gather reaches [c-1, c+M] around the particle's
   // cell, the Esirkepov window [c-M, c+M+1]; slack widens both on each side.
@@ -414,13 +429,15 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
     for (int i = 0; i < nspecies; ++i) {
       if (sp[i].np == 0) continue;
       const int32_t *src = nullptr;
+      const int64_t np_src = sp[i].np;  // a sort with open faces drops removed particles from np
       if (cadence || !sp[i].sorted) {
         PhaseTimer t(c, s, pic::kPhaseSort);
         e = pic::launch_sort(*c, sp[i], s, fold ? &src : nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "sort");
       }
+      if (sp[i].np == 0) continue;
       PhaseTimer t(c, s, pic::kPhasePush);
-      e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s, src);
+      e = pic::launch_push_deposit_tiled(*c, sp[i], *f, s, src, np_src);
       if (e != hipSuccess) {
         if (src) sp[i].sorted = 0;  // the sort's copy may not have happened: its order is not in the arrays
         return hip_fail(c, e, "push_deposit");

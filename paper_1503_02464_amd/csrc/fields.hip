@@ -75,6 +75,168 @@ __global__ void __launch_bounds__(256) k_yee_e(Yee<T> a) {
   a.Eo[2][o] += (dBy_dx - dBx_dy) - jz;
 }
 
+// ---------------------------------------------------------------------------
+// One-pass Yee step (3D): B^{n+1/2} = B^n - dt/2 curl E^n, E^{n+1} = E^n +
+// dt (curl B^{n+1/2} - J), B^{n+1} = B^{n+1/2} - dt/2 curl E^{n+1}, reading
+// E^n, B^n, J once and writing E^{n+1}, B^{n+1} into the second field set.
+//
+// A workgroup owns an xy tile of YX x YY cells and marches up through a chunk
+// of z planes.  Each thread owns one column of the tile plus its halo (x from
+// x0 - 1 to x0 + YX + 2, y from y0 - 1 to y0 + YY + 1) and keeps its own
+// column's values of the planes z and z +- 1 in registers; the x and y
+// differences read the neighbours' values of the current plane from LDS.
+// Per plane z the workgroup computes B^{n+1/2}(z) on the tile plus one
+// layer, E^{n+1}(z) on the tile plus one layer above (two in x, where the
+// Mur update of a wrapped face needs the point inside it), and B^{n+1}(z-1)
+// on the tile.  A chunk starts one plane early (B^{n+1/2} below it) and ends
+// one plane late (E^{n+1} above it), so chunks overlap by two planes of
+// recomputed values and read each input plane at most three times more.
+// With open x faces, E_y and E_z on the node planes i = 0 and i = n0 - 1
+// take the first-order Mur update from E^n of the face and the plane inside
+// it and E^{n+1} of the plane inside, before B^{n+1} uses them.
+// ---------------------------------------------------------------------------
+constexpr int kYX = 64, kYY = 8;                  // tile of output columns
+constexpr int kYPX = kYX + 4, kYPY = kYY + 3;     // columns a workgroup holds
+constexpr int kYPlane = kYPX * kYPY;              // 748
+constexpr int kYThreads = (kYPlane + 63) / 64 * 64;  // 768
+
+template <typename T>
+struct YeeFused {
+  const T *E[3], *B[3], *J[3];
+  T *Eo[3], *Bo[3];
+  int n[3];
+  int ntx, nty, nch, chunk;  // xy tiles per dimension, z chunks, planes per chunk
+  T hx, hy, hz;              // dt/2 / dx_d
+  T fx, fy, fz;              // dt / dx_d
+  T dt;
+  int open;                  // Mur on the x faces
+  T mur;                     // (dt - dx) / (dt + dx)
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kYThreads) k_yee_fused(YeeFused<T> a) {
+  __shared__ T sE[3][kYPlane];      // E^n(z)
+  __shared__ T sH[3][kYPlane];      // B^{n+1/2}(z)
+  __shared__ T sN[2][3][kYPlane];   // E^{n+1}(z - 1), E^{n+1}(z), by parity of the plane
+  // XCD-aware work order: the 8 XCDs take contiguous ranges of (xy tile,
+  // chunk) items, so the tiles whose halos overlap run on one XCD's L2.
+  const int nwork = a.ntx * a.nty * a.nch;
+  const int per = (nwork + 7) / 8;
+  const int w = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (w >= nwork) return;
+  const int ch = w % a.nch, tx = (w / a.nch) % a.ntx, ty = w / (a.nch * a.ntx);
+  const int lx = threadIdx.x % kYPX, ly = threadIdx.x / kYPX;
+  const bool mine = threadIdx.x < kYPlane;
+  const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+  // global column (periodic wrap)
+  int gx = tx * kYX - 1 + lx, gy = ty * kYY - 1 + ly;
+  gx = gx < 0 ? gx + n0 : (gx >= n0 ? gx - n0 : gx);
+  gy = gy < 0 ? gy + n1 : (gy >= n1 ? gy - n1 : gy);
+  const int64_t col = gx + (int64_t)n0 * gy, plane = (int64_t)n0 * n1;
+  // regions in local column coordinates
+  const bool r2 = mine && lx < kYX + 3 && ly < kYY + 2;                                    // B^{n+1/2}
+  const bool r1 = mine && lx >= 1 && lx < kYX + 3 && ly >= 1 && ly < kYY + 2;              // E^{n+1}
+  const bool out = mine && lx >= 1 && lx < kYX + 1 && ly >= 1 && ly < kYY + 1;             // written
+  const int me = ly * kYPX + lx;
+  const int zs = ch * a.chunk, ze = zs + a.chunk < n2 ? zs + a.chunk : n2;
+  auto zw = [&](int z) { return z < 0 ? z + n2 : (z >= n2 ? z - n2 : z); };
+  auto ld = [&](const T *const F[3], int z, T v[3], bool on) {
+    const int64_t o = col + plane * zw(z);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = on ? F[c][o] : T(0);
+  };
+  // Mur: which face this column is (0 none, 1 low, 2 high) and the column inside it
+  const int face = (a.open && r1) ? (gx == 0 ? 1 : (gx == n0 - 1 ? 2 : 0)) : 0;
+  const int inner = face == 1 ? me + 1 : (face == 2 ? me - 1 : me);
+
+  T E0[3], E1[3], Bn[3], Jn[3], pE[3], pB[3], pJ[3], H0[3], H1[3], N0[3], N1[3];
+  ld(a.E, zs - 1, E0, mine);
+  ld(a.E, zs, E1, mine);
+  ld(a.B, zs - 1, Bn, r2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Jn[c] = H0[c] = H1[c] = N0[c] = N1[c] = T(0);
+  ld(a.E, zs + 1, pE, mine);
+  ld(a.B, zs, pB, r2);
+  ld(a.J, zs, pJ, r1);
+  for (int z = zs - 1; z <= ze; ++z) {
+    // E^n(z) to LDS
+    if (mine) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sE[c][me] = E0[c];
+    }
+    __syncthreads();
+    // B^{n+1/2}(z) = B^n(z) - dt/2 curl E^n (forward differences)
+    if (r2) {
+      const T dEz_dy = sE[2][me + kYPX] - E0[2], dEx_dy = sE[0][me + kYPX] - E0[0];
+      const T dEz_dx = sE[2][me + 1] - E0[2], dEy_dx = sE[1][me + 1] - E0[1];
+      const T dEy_dz = E1[1] - E0[1], dEx_dz = E1[0] - E0[0];
+      H1[0] = Bn[0] - (a.hy * dEz_dy - a.hz * dEy_dz);
+      H1[1] = Bn[1] - (a.hz * dEx_dz - a.hx * dEz_dx);
+      H1[2] = Bn[2] - (a.hx * dEy_dx - a.hy * dEx_dy);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sH[c][me] = H1[c];
+    }
+    __syncthreads();
+    // E^{n+1}(z) = E^n(z) + dt (curl B^{n+1/2} - J) (backward differences)
+    const int cur = z & 1;
+    if (z >= zs) {
+      if (r1) {
+        const T dBz_dy = H1[2] - sH[2][me - kYPX], dBx_dy = H1[0] - sH[0][me - kYPX];
+        const T dBz_dx = H1[2] - sH[2][me - 1], dBy_dx = H1[1] - sH[1][me - 1];
+        const T dBy_dz = H1[1] - H0[1], dBx_dz = H1[0] - H0[0];
+        N1[0] = E0[0] + ((a.fy * dBz_dy - a.fz * dBy_dz) - a.dt * Jn[0]);
+        N1[1] = E0[1] + ((a.fz * dBx_dz - a.fx * dBz_dx) - a.dt * Jn[1]);
+        N1[2] = E0[2] + ((a.fx * dBy_dx - a.fy * dBx_dy) - a.dt * Jn[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sN[cur][c][me] = N1[c];
+      }
+      if (a.open) {  // uniform over the workgroup
+        __syncthreads();
+        if (face) {
+#pragma unroll
+          for (int c = 1; c < 3; ++c) {
+            N1[c] = sE[c][inner] + a.mur * (sN[cur][c][inner] - E0[c]);
+          }
+        }
+        __syncthreads();
+        if (face) {
+#pragma unroll
+          for (int c = 1; c < 3; ++c) sN[cur][c][me] = N1[c];
+        }
+      }
+    }
+    __syncthreads();
+    // B^{n+1}(z - 1) = B^{n+1/2}(z - 1) - dt/2 curl E^{n+1}, and E^{n+1}(z - 1), out
+    if (z >= zs + 1 && out) {
+      const int prv = cur ^ 1;
+      const T dEz_dy = sN[prv][2][me + kYPX] - N0[2], dEx_dy = sN[prv][0][me + kYPX] - N0[0];
+      const T dEz_dx = sN[prv][2][me + 1] - N0[2], dEy_dx = sN[prv][1][me + 1] - N0[1];
+      const T dEy_dz = N1[1] - N0[1], dEx_dz = N1[0] - N0[0];
+      const int64_t o = col + plane * zw(z - 1);
+      a.Bo[0][o] = H0[0] - (a.hy * dEz_dy - a.hz * dEy_dz);
+      a.Bo[1][o] = H0[1] - (a.hz * dEx_dz - a.hx * dEz_dx);
+      a.Bo[2][o] = H0[2] - (a.hx * dEy_dx - a.hy * dEx_dy);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.Eo[c][o] = N0[c];
+    }
+    // next plane
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      E0[c] = E1[c];
+      E1[c] = pE[c];
+      Bn[c] = pB[c];
+      Jn[c] = pJ[c];
+      H0[c] = H1[c];
+      N0[c] = N1[c];
+    }
+    if (z + 1 < ze) {  // the planes iteration z + 2 needs (the last one, ze, needs none beyond)
+      ld(a.E, z + 3, pE, mine);
+      ld(a.B, z + 2, pB, r2);
+      ld(a.J, z + 2, pJ, r1);
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_zero(T *p, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -159,7 +321,58 @@ __global__ void __launch_bounds__(256) k_laser(T *J, int plane, int n0, int n1, 
   J[plane + (int64_t)n0 * jk] += static_cast<T>(amp * exp(-(y * y + z * z) * inv_w02));
 }
 
+
+bool yee_fused_supported(const pic_ctx &c) {
+  return c.p.dims == 3 && c.n[0] % kYX == 0 && c.n[1] % kYY == 0 && c.n[2] >= 2;
+}
+
+template <typename T>
+hipError_t yee_fused_impl(const pic_ctx &c, const pic_fields &f, hipStream_t s) {
+  YeeFused<T> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.E[d] = static_cast<const T *>(f.E[d]);
+    a.B[d] = static_cast<const T *>(f.B[d]);
+    a.J[d] = static_cast<const T *>(f.J[d]);
+    a.Eo[d] = static_cast<T *>(f.E_alt[d]);
+    a.Bo[d] = static_cast<T *>(f.B_alt[d]);
+    a.n[d] = static_cast<int>(c.n[d]);
+  }
+  a.ntx = static_cast<int>(c.n[0] / kYX);
+  a.nty = static_cast<int>(c.n[1] / kYY);
+  // enough (tile, chunk) items for two workgroups per CU, chunks of at least 4 planes
+  int nch = (512 + a.ntx * a.nty - 1) / (a.ntx * a.nty);
+  const int most = static_cast<int>(c.n[2] / 4) > 1 ? static_cast<int>(c.n[2] / 4) : 1;
+  nch = nch < 1 ? 1 : (nch > most ? most : nch);
+  a.chunk = static_cast<int>((c.n[2] + nch - 1) / nch);
+  a.nch = static_cast<int>((c.n[2] + a.chunk - 1) / a.chunk);
+  const double dt = c.p.dt;
+  a.hx = static_cast<T>(0.5 * dt / c.p.dx[0]);
+  a.hy = static_cast<T>(0.5 * dt / c.p.dx[1]);
+  a.hz = static_cast<T>(0.5 * dt / c.p.dx[2]);
+  a.fx = static_cast<T>(dt / c.p.dx[0]);
+  a.fy = static_cast<T>(dt / c.p.dx[1]);
+  a.fz = static_cast<T>(dt / c.p.dx[2]);
+  a.dt = static_cast<T>(dt);
+  a.open = c.p.open_x;
+  a.mur = static_cast<T>((dt - c.p.dx[0]) / (dt + c.p.dx[0]));
+  const int64_t nwork = static_cast<int64_t>(a.ntx) * a.nty * a.nch;
+  const unsigned blocks = static_cast<unsigned>((nwork + 7) / 8 * 8);
+  hipLaunchKernelGGL(k_yee_fused<T>, dim3(blocks), dim3(kYThreads), 0, s, a);
+  return hipGetLastError();
+}
 }  // namespace
+
+bool yee_fused_ok(const pic_ctx &c, const pic_fields &f) {
+  if (!yee_fused_supported(c)) return false;
+  for (int d = 0; d < 3; ++d)
+    if (!f.E_alt[d] || !f.B_alt[d]) return false;
+  return true;
+}
+
+hipError_t launch_yee_fused(const pic_ctx &c, const pic_fields &f, hipStream_t s) {
+  if (!yee_fused_ok(c, f)) return hipErrorInvalidValue;
+  return c.p.precision == PIC_FP64 ? yee_fused_impl<double>(c, f, s) : yee_fused_impl<float>(c, f, s);
+}
 
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s) {
   const int bs = yee_block(c);

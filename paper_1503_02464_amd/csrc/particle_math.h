@@ -381,6 +381,30 @@ __device__ __forceinline__ void deposit(const Acc &acc, const int c0[3], const T
 
 // ---- accessors ------------------------------------------------------------
 
+// One addition into an on-chip current accumulator of type S.  Floating
+// accumulators add the value; the 64-bit fixed-point one (unsigned long long,
+// two's complement) adds v 2^shift rounded to the nearest integer, where
+// shift keeps every contribution of the launch within 2^30.
+template <typename S, typename V>
+__device__ __forceinline__ void lds_add(S *p, V v, int) {
+  atomicAdd(p, static_cast<S>(v));
+}
+template <typename V>
+__device__ __forceinline__ void lds_add(unsigned long long *p, V v, int shift) {
+  const int k = static_cast<int>(rintf(ldexpf(static_cast<float>(v), shift)));
+  atomicAdd(p, static_cast<unsigned long long>(static_cast<long long>(k)));
+}
+
+// The value an accumulator holds, in the state's type T.
+template <typename T, typename S>
+__device__ __forceinline__ T lds_value(S a, int) {
+  return static_cast<T>(a);
+}
+template <typename T>
+__device__ __forceinline__ T lds_value(unsigned long long a, int shift) {
+  return static_cast<T>(ldexp(static_cast<double>(static_cast<long long>(a)), -shift));
+}
+
 // Fields in HBM with periodic wrap (indices at most a few cells outside).
 template <typename T>
 struct GlobalFields {
@@ -423,12 +447,13 @@ struct LdsFields {
 template <typename S, int SX, int SXY, int VOL, int OX, int OY, int OZ>
 struct LdsBox {
   S *base;
+  int shift;  // fixed-point accumulators only
   __device__ __forceinline__ S load(int comp, int i, int j, int k) const {
     return base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)];
   }
   template <typename V>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
-    atomicAdd(&base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)], static_cast<S>(v));
+    lds_add(&base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)], v, shift);
   }
 };
 
@@ -436,9 +461,10 @@ template <typename S>
 struct LdsCurrent {
   S *base;
   int sx, sxy, vol, o0, o1, o2;
+  int shift;
   template <typename V>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
-    atomicAdd(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], static_cast<S>(v));
+    lds_add(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], v, shift);
   }
 };
 

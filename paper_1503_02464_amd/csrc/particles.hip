@@ -4,6 +4,8 @@
 // HBM once.  Dispatch over precision x dimensions x shape order.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "particle_math.h"
 #include "pic_internal.h"
 
@@ -27,6 +29,7 @@ struct SpeciesArgs {
   // copy it takes over) and writes it to the *_o arrays, which otherwise are
   // the arrays above.
   const int32_t *src;
+  int64_t np_src;  // particles in the arrays src indexes (a sort may have dropped removed ones since)
   int32_t *cell_o;
   T *off_o[3];
   T *u_o[3];
@@ -99,7 +102,8 @@ __device__ __forceinline__ double lane_push(int to, double v) {
 // through per-lane strides.
 template <typename T, int M, typename S>
 __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jvol, int jlo, const int c0[3],
-                                                  const T o0[3], const int dc[3], const T o1[3], const T jc[3]) {
+                                                  const T o0[3], const int dc[3], const T o1[3], const T jc[3],
+                                                  int shift) {
   constexpr int WN = M + 1, WW = M + 2;  // narrow and wide node counts
   bool cr[3];
 #pragma unroll
@@ -145,7 +149,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
           const T t = e.A[1][j] * e.S0[2][k] + e.Bf[1][j] * e.DS[2][k];
 #pragma unroll
           for (int i = 0; i < WW - 1; ++i)
-            atomicAdd(&jl[cb[0] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[0] * e.CDS[0][i] * t));
+            lds_add(&jl[cb[0] + org + i * st[0] + j * st[1] + k * st[2]], -pc[0] * e.CDS[0][i] * t, shift);
         }
   // along the second axis
 #pragma unroll
@@ -157,7 +161,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 #pragma unroll
         for (int j = 0; j < WW - 1; ++j)
           if (j < WN - 1 || wide[1])
-            atomicAdd(&jl[cb[1] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[1] * e.CDS[1][j] * t));
+            lds_add(&jl[cb[1] + org + i * st[0] + j * st[1] + k * st[2]], -pc[1] * e.CDS[1][j] * t, shift);
       }
   // along the third axis
 #pragma unroll
@@ -169,7 +173,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 #pragma unroll
         for (int k = 0; k < WW - 1; ++k)
           if (k < WN - 1 || wide[2])
-            atomicAdd(&jl[cb[2] + org + i * st[0] + j * st[1] + k * st[2]], static_cast<S>(-pc[2] * e.CDS[2][k] * t));
+            lds_add(&jl[cb[2] + org + i * st[0] + j * st[1] + k * st[2]], -pc[2] * e.CDS[2][k] * t, shift);
       }
 }
 
@@ -180,7 +184,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 template <typename T, int M, typename S>
 __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, int jlo, const int c0[3],
                                                      const T o0[3], const int dc[3], const T o1[3], const T jc[3],
-                                                     T jzc) {
+                                                     T jzc, int shift) {
   constexpr int WN = M + 1, WW = M + 2;
   bool cr[2];
 #pragma unroll
@@ -210,7 +214,7 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
       const T t = e.A[1][j];
 #pragma unroll
       for (int i = 0; i < WW - 1; ++i)
-        atomicAdd(&jl[cb[0] + org + i * st[0] + j * st[1]], static_cast<S>(-pc[0] * e.CDS[0][i] * t));
+        lds_add(&jl[cb[0] + org + i * st[0] + j * st[1]], -pc[0] * e.CDS[0][i] * t, shift);
     }
   // along the other in-plane axis
 #pragma unroll
@@ -219,7 +223,7 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
 #pragma unroll
     for (int j = 0; j < WW - 1; ++j)
       if (j < WN - 1 || wide1)
-        atomicAdd(&jl[cb[1] + org + i * st[0] + j * st[1]], static_cast<S>(-pc[1] * e.CDS[1][j] * t));
+        lds_add(&jl[cb[1] + org + i * st[0] + j * st[1]], -pc[1] * e.CDS[1][j] * t, shift);
   }
   // out of the plane
   if (jzc != T(0))
@@ -228,8 +232,8 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
       if (j < WN || wide1)
 #pragma unroll
         for (int i = 0; i < WW; ++i)
-          atomicAdd(&jl[2 * jvol + org + i * st[0] + j * st[1]],
-                    static_cast<S>(jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j])));
+          lds_add(&jl[2 * jvol + org + i * st[0] + j * st[1]], jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j]),
+                  shift);
 }
 
 template <typename T, int D>
@@ -353,6 +357,21 @@ struct TileArgs {
   int cross_cap;           // entries of the LDS list of wide-window particles
 };
 
+// The power-of-two shift of a tile's fixed-point current: every contribution
+// is bounded by max_d |jc_d| w_max (2D J_z: |jz| w_max, since |v_z| < 1),
+// w_max the largest |w| among the tile's particles, and the shift brings that
+// bound to at most 2^30.
+template <typename T>
+__device__ __forceinline__ int fixed_shift(const SpeciesArgs<T> &s, float wmax, int dims) {
+  float c = fmaxf(fabsf(static_cast<float>(s.jc[0])), fabsf(static_cast<float>(s.jc[1])));
+  c = fmaxf(c, fabsf(static_cast<float>(dims == 3 ? s.jc[2] : s.jz)));
+  c *= wmax;
+  if (!(c > 0.f) || !isfinite(c)) return 0;
+  int e = 0;
+  frexpf(c, &e);  // c < 2^e
+  return 30 - e;
+}
+
 // Tile geometry known at compile time: LDS offsets fold into immediates.
 template <int D, int M, int LX, int LY, int LZ, int SL>
 struct FixedGeom {
@@ -384,13 +403,13 @@ template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
 struct FieldBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
   using G = FixedGeom<D, M, LX, LY, LZ, SL>;
   using type = LdsBox<T, G::FX, G::FX * G::FY, G::FVOL, G::FLO, G::FLO, D == 3 ? G::FLO : 0>;
-  __device__ static type make(T *base, const G &) { return type{base}; }
+  __device__ static type make(T *base, const G &) { return type{base, 0}; }
 };
 template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
 struct CurrentBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
   using G = FixedGeom<D, M, LX, LY, LZ, SL>;
   using type = LdsBox<T, G::JX, G::JXY, G::JVOL, G::JLO, G::JLO, D == 3 ? G::JLO : 0>;
-  __device__ static type make(T *base, const G &) { return type{base}; }
+  __device__ static type make(T *base, const G &, int shift) { return type{base, shift}; }
 };
 template <typename T, int DD>
 struct FieldBox<T, RuntimeGeom, DD> {
@@ -402,8 +421,8 @@ struct FieldBox<T, RuntimeGeom, DD> {
 template <typename T, int DD>
 struct CurrentBox<T, RuntimeGeom, DD> {
   using type = LdsCurrent<T>;
-  __device__ static type make(T *base, const RuntimeGeom &g) {
-    return type{base, g.JX, g.JXY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0};
+  __device__ static type make(T *base, const RuntimeGeom &g, int shift) {
+    return type{base, g.JX, g.JXY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0, shift};
   }
 };
 
@@ -452,6 +471,8 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   int32_t *xk = reinterpret_cast<int32_t *>(xw + 2 * CAP);  // [CAP]: local cell and cell change
   int32_t *xn = xk + CAP;                                    // list length
   int32_t *slot = xn + 1;                                    // the item this workgroup takes next
+  uint32_t *wbits = reinterpret_cast<uint32_t *>(slot + 1);  // bits of the tile's largest |w| (fixed point)
+  constexpr bool kFixed = sizeof(TJ) == 8 && !std::is_floating_point<TJ>::value;
   // the merge clears the box behind it, so it is zeroed once here
   for (int idx = threadIdx.x; idx < 3 * geo.JVOL; idx += BLOCK) jl[idx] = TJ(0);
   // A box index T0 - lo + l (0 <= l < X, lo < X, T0 <= n - L) lies in
@@ -476,6 +497,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       }
       *slot = static_cast<int32_t>(it);
       *xn = 0;
+      *wbits = 0u;
     }
     __syncthreads();
     const int64_t item = *slot;
@@ -509,11 +531,27 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     };
     if (once) stage(near_wrap);
     else stage(full_wrap);
+    // the tile's largest |w| sets the fixed-point scale of its current box
+    // (the main loop then reads the weights again, from the L2)
+    if constexpr (kFixed) {
+      float wm = 0.f;
+      for (int64_t q = pbeg + threadIdx.x; q < pend; q += BLOCK) {
+        int64_t r = q;
+        if constexpr (FOLD) {
+          r = s.src[q];
+          r = r >= 0 && r < s.np_src ? r : -1;
+        }
+        if (r >= 0) wm = fmaxf(wm, fabsf(static_cast<float>(s.w[r])));
+      }
+      for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));
+      if (__lane_id() == 0) atomicMax(wbits, __float_as_uint(wm));
+    }
     __syncthreads();
+    const int shift = kFixed ? fixed_shift<T>(s, __uint_as_float(*wbits), D) : 0;
 
     // local frames: the tile origin is (0,0,0)
     const auto lf = FieldBox<T, G, D>::make(fl, geo);
-    const auto lj = CurrentBox<TJ, G, D>::make(jl, geo);
+    const auto lj = CurrentBox<TJ, G, D>::make(jl, geo, shift);
     const int lane = __lane_id();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -529,7 +567,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     // sort left inconsistent, which it flagged)
     auto from = [&](int64_t q) -> int64_t {
       const int64_t r = s.src[q];
-      return r >= 0 && r < s.np ? r : -1;
+      return r >= 0 && r < s.np_src ? r : -1;
     };
     int64_t n_r = -1;
     if constexpr (FOLD) {
@@ -728,9 +766,9 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       const T w = xw[k];
       const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
       if constexpr (D == 3)
-        esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc);
+        esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, shift);
       else
-        esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, w * xw[CAP + k]);
+        esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, w * xw[CAP + k], shift);
     }
     __syncthreads();
 
@@ -747,7 +785,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         const int64_t gidx = gi + (int64_t)g.n[0] * (gjj + (int64_t)g.n[1] * gk);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T v = static_cast<T>(jl[c * geo.JVOL + idx]);
+          const T v = lds_value<T>(jl[c * geo.JVOL + idx], shift);
           jl[c * geo.JVOL + idx] = TJ(0);  // ready for the next tile
           if (v != T(0)) unsafeAtomicAdd(&gj.J[c][gidx], v);
         }
@@ -806,7 +844,7 @@ __global__ void __launch_bounds__(256) k_fold_tail(SpeciesArgs<T> s, const int32
   lo = lo < 0 ? 0 : lo;
   for (int64_t q = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < s.np; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = s.src[q];
-    if (r < 0 || r >= s.np) continue;  // only after a flagged inconsistency
+    if (r < 0 || r >= s.np_src) continue;  // only after a flagged inconsistency
     s.cell_o[q] = s.cell[r];
 #pragma unroll
     for (int d = 0; d < D; ++d) s.off_o[d][q] = s.off[d][r];
@@ -830,6 +868,7 @@ SpeciesArgs<T> species_args(const pic_ctx &c, const pic_species &sp) {
   }
   s.w = static_cast<T *>(sp.w);
   s.src = nullptr;
+  s.np_src = sp.np;
   s.cell_o = s.cell;
   for (int d = 0; d < 3; ++d) {
     s.off_o[d] = s.off[d];
@@ -932,12 +971,13 @@ hipError_t launch_tiled_acc(const pic_ctx &c, const SpeciesArgs<T> &sa, const pi
   return hipGetLastError();
 }
 
-// The LDS current box is accumulated in double unless the caller asked for
-// FP32 accumulation of an FP32 state.
+// The LDS current box of an FP32 state is accumulated in 64-bit fixed point
+// (default), double or float; an FP64 state's in double.
 template <typename T, int D, int M, class G, int BLOCK>
 hipError_t launch_tiled(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                         hipStream_t st) {
   if constexpr (sizeof(T) == 4) {
+    if (c.accfix) return launch_tiled_acc<T, D, M, G, BLOCK, unsigned long long>(c, sa, f, t, st);
     if (!c.acc64) return launch_tiled_acc<T, D, M, G, BLOCK, float>(c, sa, f, t, st);
   }
   return launch_tiled_acc<T, D, M, G, BLOCK, double>(c, sa, f, t, st);
@@ -946,12 +986,14 @@ hipError_t launch_tiled(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fi
 // Tile shapes with a compile-time instantiation; other shapes use the
 // runtime-geometry kernel.
 template <typename T, int D, int M>
-hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t st, const int32_t *src) {
+hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t st, const int32_t *src,
+                      int64_t np_src) {
   if (sp.np == 0) return hipSuccess;
   if (D != 3 && src) return hipErrorInvalidValue;  // only 3D launches fold a sort's copy
   SpeciesArgs<T> sa = species_args<T>(c, sp);
   if (src) {  // read through the sort's slots, write the second set
     sa.src = src;
+    sa.np_src = np_src;
     sa.cell_o = sp.cell_alt;
     for (int d = 0; d < 3; ++d) {
       sa.off_o[d] = static_cast<T *>(sp.off_alt[d]);
@@ -1044,8 +1086,8 @@ hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fie
 }
 
 hipError_t launch_push_deposit_tiled(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t s,
-                                     const int32_t *src) {
-  PIC_DISPATCH(tiled_impl, c, sp, f, s, src);
+                                     const int32_t *src, int64_t np_src) {
+  PIC_DISPATCH(tiled_impl, c, sp, f, s, src, np_src);
 }
 
 }  // namespace pic

@@ -81,7 +81,8 @@ struct pic_ctx {
   int32_t jxy = 1;  // plane stride of the current box (current_plane_stride)
   int32_t gf_lo[3] = {0, 0, 0}, gj_lo[3] = {0, 0, 0};
   size_t lds_bytes = 0;
-  bool acc64 = true;  // LDS current box accumulated in double
+  bool acc64 = true;  // LDS current box 8 bytes per value (double or 64-bit fixed point)
+  bool accfix = false;  // LDS current box in 64-bit fixed point (FP32 state)
   int32_t cross_cap = 0;  // capacity of the fused kernel's wide-window list
   int32_t levels = 32;  // rank levels per tile in the sort (particles sharing a node go to distinct levels)
   // (tile_start array, particle count) of every species this context sorted
@@ -122,10 +123,11 @@ namespace pic {
 hipError_t launch_gather_push(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fields &f, hipStream_t s);
 // src: when not null, the slots of a sort whose copy was left to this launch
-// (particle q of the sorted order is particle src[q] of the current set); the
+// (particle q of the sorted order is particle src[q] of the current set, which
+// holds np_src particles: the sort may have dropped removed ones from np); the
 // launch writes every particle into the second set and swaps the sets.
 hipError_t launch_push_deposit_tiled(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t s,
-                                     const int32_t *src = nullptr);
+                                     const int32_t *src = nullptr, int64_t np_src = 0);
 hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
 // Open x faces: save = true keeps E_y, E_z^n next to the faces (before the E
 // update), save = false applies the Mur update to the faces (after it).
@@ -133,6 +135,10 @@ hipError_t launch_mur(const pic_ctx &c, const pic_fields &f, bool save, hipStrea
 // J += the registered laser sheet at time t.
 hipError_t launch_laser(const pic_ctx &c, const pic_fields &f, double t, hipStream_t s);
 hipError_t launch_yee_b(const pic_ctx &c, const pic_fields &f, double frac, hipStream_t s);
+// The one-pass Yee step into the second field set (3D; x and y divisible by
+// its tile; f.E_alt and f.B_alt set), and whether it applies.
+bool yee_fused_ok(const pic_ctx &c, const pic_fields &f);
+hipError_t launch_yee_fused(const pic_ctx &c, const pic_fields &f, hipStream_t s);
 // E += frac dt curl B (- dt J when with_j)
 hipError_t launch_yee_e(const pic_ctx &c, const pic_fields &f, hipStream_t s, double frac = 1.0, bool with_j = true);
 // Adjoint kernels.
@@ -147,6 +153,7 @@ void swap_sets(pic_species &sp);
 // The non-empty tiles of a species' last sort (list, count at [ntiles]), or
 // null when this context has not sorted that species.
 const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp);
+
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,

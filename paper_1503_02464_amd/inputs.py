@@ -8,6 +8,11 @@ per-dimension (cell index, offset) form, plus random field arrays.
 * Momenta u = p/(m c): each component drawn from N(0, sigma^2), no mean removed.
 * Weights: a constant supplied by the caller.
 
+Two counter-streaming beams (the two-stream workload): ``two_beams`` places
+``ppc`` particles per cell per beam at uniform random offsets with mean
+momenta +-u0 along x; ``quiet_beams`` places them on a regular sub-lattice of
+every cell (the same points for both beams) with u_x = +-u0 + eps sin(k x).
+
 ``round_f32`` snaps a state onto float32-representable values (offsets stay
 strictly below 1) so the FP32 path and the FP64 oracle start from the same
 numbers.
@@ -118,3 +123,39 @@ def round_f32(sp: dict) -> dict:
 
 def round_fields_f32(f: dict) -> dict:
     return {k: np.ascontiguousarray(v.astype(np.float32).astype(np.float64)) for k, v in f.items()}
+
+
+def two_beams(n: tuple, dims: int, ppc: int, u0: float, u_sigma: float, weight: float, seed: int,
+              q: float = -1.0, m: float = 1.0) -> tuple:
+    """Two beams of ``ppc`` particles per cell each, offsets uniform, momenta
+    Gaussian (spread u_sigma) about (+u0, 0, 0) and (-u0, 0, 0)."""
+    a = uniform_plasma(n, dims, ppc, u_sigma, weight, seed, q=q, m=m, u_mean=(u0, 0.0, 0.0))
+    b = uniform_plasma(n, dims, ppc, u_sigma, weight, seed + 1, q=q, m=m, u_mean=(-u0, 0.0, 0.0))
+    return a, b
+
+
+def quiet_beams(n: tuple, dims: int, sub: tuple, u0: float, eps: float, k: float, dx: float, weight: float,
+                q: float = -1.0, m: float = 1.0) -> tuple:
+    """Two cold beams on the same regular sub-lattice of sub[0] x sub[1] (x sub[2])
+    points per cell (offsets (i + 1/2)/sub), with u_x = +-u0 + eps sin(k x) at
+    x = (cell + offset) dx: a quiet start with one seeded mode."""
+    ncell = int(n[0] * n[1] * n[2])
+    per = int(np.prod(sub[:dims]))
+    lin = np.repeat(np.arange(ncell, dtype=np.int64), per)
+    npart = ncell * per
+    cell = np.zeros((3, npart), np.int32)
+    cell[0] = lin % n[0]
+    cell[1] = (lin // n[0]) % n[1]
+    cell[2] = lin // (n[0] * n[1])
+    grids = np.meshgrid(*[(np.arange(sub[d]) + 0.5) / sub[d] for d in range(dims)], indexing="ij")
+    off = np.zeros((3, npart), np.float64)
+    for d in range(dims):
+        off[d] = np.tile(grids[d].ravel(), ncell)
+    x = (cell[0] + off[0]) * dx
+    out = []
+    for sign in (1.0, -1.0):
+        u = np.zeros((3, npart))
+        u[0] = sign * u0 + eps * np.sin(k * x)
+        out.append({"q": float(q), "m": float(m), "cell": cell.copy(), "off": off.copy(), "u": u,
+                    "w": np.full(npart, weight, np.float64)})
+    return tuple(out)

@@ -68,7 +68,8 @@ class Simulation:
     dims 2 or 3; n cells per dim (n[2] = 1 in 2D); dx spacings; dt step;
     order 1 (linear) or 2 (quadratic); precision "fp32" or "fp64"; tile cells
     per sort tile; slack guard cells; sort_every steps between sorts;
-    current_accum the LDS current accumulation type ("auto" = fp64); open_x
+    current_accum the LDS current accumulation type ("auto": fix64 for an
+    fp32 state, fp64 for an fp64 state; "fp64", "fix64", "fp32"); open_x
     opens the x faces (Mur fields, particles removed outside
     [absorb, n0 - absorb) cells); sort_levels the levels per tile of the sort
     (0: the library's default)."""
@@ -76,7 +77,7 @@ class Simulation:
     def __init__(self, dims: int, n: tuple, dx: tuple, dt: float, order: int, precision: str = "fp32",
                  tile: tuple = (8, 8, 8), slack: int = 1, sort_every: int = 4, max_particles: int = 0,
                  current_accum: str = "auto", open_x: bool = False, absorb: int = 0, sort_levels: int = 0,
-                 device: str = "cuda"):
+                 device: str = "cuda", field_sets: int = 2):
         self.lib = L.load()
         self.dims = dims
         self.n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
@@ -101,7 +102,8 @@ class Simulation:
         p.sort_every = sort_every
         self.sort_every = int(sort_every)
         p.max_particles = int(max_particles)
-        p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64}[current_accum]
+        p.current_accum = {"auto": L.PIC_ACC_AUTO, "fp32": L.PIC_ACC_FP32, "fp64": L.PIC_ACC_FP64,
+                           "fix64": L.PIC_ACC_FIX64}[current_accum]
         p.open_x = 1 if open_x else 0
         p.absorb = int(absorb)
         p.sort_levels = int(sort_levels)
@@ -124,6 +126,16 @@ class Simulation:
         self.fstruct = L.Fields()
         for k in ("E", "B", "J"):
             setattr(self.fstruct, k, L._c3p(*[_ptr(t) for t in self.fields[k]]))
+        # a second E, B set lets the library run the Yee step in one pass and swap the sets
+        self._field_pool = {}
+        if field_sets == 2:
+            self.fields_alt = {k: [torch.zeros(self.ncells, dtype=self.dtype, device=self.device) for _ in range(3)]
+                               for k in ("E", "B")}
+            for k in ("E", "B"):
+                setattr(self.fstruct, k + "_alt", L._c3p(*[_ptr(t) for t in self.fields_alt[k]]))
+            for k in ("E", "B"):
+                for t in self.fields[k] + self.fields_alt[k]:
+                    self._field_pool[_ptr(t)] = t
         bits = (ctypes.c_int32 * 3)()
         self.lib.pic_cell_bits(ctx, bits)
         self.bits = tuple(bits)
@@ -133,6 +145,16 @@ class Simulation:
     # -- plumbing ---------------------------------------------------------
     def _call(self, status: int, what: str) -> None:
         L.check(self.lib, self.ctx, status, what)
+
+    def _sync_fields(self) -> None:
+        """Follow the library's swaps of the two E, B sets: self.fields names
+        the tensors the struct's current pointers name."""
+        if not self._field_pool:
+            return
+        for k in ("E", "B"):
+            cur = [self._field_pool[p] for p in getattr(self.fstruct, k)]
+            alt = [self._field_pool[p] for p in getattr(self.fstruct, k + "_alt")]
+            self.fields[k], self.fields_alt[k] = cur, alt
 
     def close(self) -> None:
         if getattr(self, "ctx", None):
@@ -239,8 +261,11 @@ class Simulation:
                    "pic_zero_current")
 
     def yee_step(self) -> None:
-        self._call(self.lib.pic_yee_step(self.ctx, ctypes.byref(self.fstruct), ctypes.c_void_p(_stream())),
-                   "pic_yee_step")
+        try:
+            self._call(self.lib.pic_yee_step(self.ctx, ctypes.byref(self.fstruct), ctypes.c_void_p(_stream())),
+                       "pic_yee_step")
+        finally:
+            self._sync_fields()
 
     def set_laser(self, plane: int, e0: float, omega: float = 1.0, w0: float = 1e30, tau: float = 1e30,
                   t0: float = 0.0, yc: float = 0.0, zc: float = 0.0, pol: int = 1) -> None:
@@ -276,6 +301,7 @@ class Simulation:
             for i, s in enumerate(sp):  # particles or cleared sorted
                 s.struct = arr[i]
                 s.np = int(arr[i].np)
+            self._sync_fields()
 
     def diagnostics(self, species: list | None = None) -> dict:
         sp = species if species is not None else self.species

@@ -89,7 +89,7 @@ def test_cfl_limit(lib, cfl, want):
     dict(sort_every=-1), dict(slack=5), dict(maxp=-1), dict(dx=(0.05, 0.0, 0.05)),
     dict(n=(64, 64, 64), tile=(32, 8, 8)),  # local cells must fit the packed 6-bit range
     dict(prec=L.PIC_FP64, tile=(16, 16, 16), n=(32, 32, 32)),  # LDS tile beyond 160 KB
-    dict(acc=3), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32),
+    dict(acc=4), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FP32), dict(prec=L.PIC_FP64, acc=L.PIC_ACC_FIX64),
     dict(open_x=2), dict(open_x=1, absorb=5),  # absorb below 2 * order + 2
     dict(open_x=1, absorb=8),  # n[0] < 2 * absorb + 2
     dict(sort_levels=1), dict(sort_levels=129),

@@ -41,6 +41,35 @@ def test_yee_step(prec, dims):
     s.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,open_x", [((64, 16, 6), False), ((128, 8, 5), True), ((64, 8, 4), False)],
+                         ids=["periodic", "open-two-x-tiles", "one-chunk"])
+def test_yee_step_one_pass(prec, n, open_x):
+    """The one-pass Yee step into the second field set (3D, x a multiple of 64,
+    y of 8) against the oracle's three-part update, three steps in a row, so
+    the field sets swap back and forth; with open x faces the Mur update runs
+    inside the pass."""
+    from paper_1503_02464_amd.sim import Simulation
+    g = grid(3, n, dx=0.05, cfl=0.7, order=2)
+    f = inputs.random_fields(g.ncells, 1.0, seed=23)
+    f["J"] = inputs.rng(24).normal(size=(3, g.ncells))
+    if prec == "fp32":
+        f = inputs.round_fields_f32(f)
+    kw = dict(open_x=True, absorb=6) if open_x else {}
+    s = Simulation(3, g.n, g.dx, g.dt, 2, prec, tile=(8, 4, 1), max_particles=1, **kw)
+    assert s.lib.pic_tile_lds_bytes(s.ctx) > 0
+    s.set_fields(f["E"], f["B"], f["J"])
+    ref = {k: v.copy() for k, v in f.items()}
+    first = [t.data_ptr() for t in s.fields["E"]]
+    for step in range(3):
+        s.yee_step()
+        (O.yee_step_open if open_x else O.yee_step)(g, ref)
+        swapped = [t.data_ptr() for t in s.fields["E"]] != first
+        assert swapped == (step % 2 == 0), "the one-pass step writes the second set and swaps"
+        compare_fields(prec, s.get_fields(), ref, keys=("E", "B"), what=f"one-pass yee, step {step}")
+    s.close()
+
+
 @pytest.mark.parametrize("prec,dims,order", VARIANTS, ids=VID)
 def test_unfused_gather_push_deposit(prec, dims, order):
     g = small_grid(dims, order)

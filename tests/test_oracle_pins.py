@@ -26,3 +26,9 @@ assert len(IDS) == len(pins.ALL_PINS)
 @pytest.mark.parametrize("pin", pins.ALL_PINS, ids=IDS)
 def test_pin(pin):
     pin()
+
+
+def test_two_stream_growth_rate():
+    """The whole FP64 loop against the cold two-stream growth rate (kept out of
+    the mutant sweep, which runs every pin per planted mistake, for its length)."""
+    pins.pin_two_stream_growth()
