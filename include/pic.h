@@ -281,6 +281,23 @@ pic_status pic_diagnostics(pic_ctx *ctx, const pic_species *sp, int32_t nspecies
 pic_status pic_charge_density(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
                               double *rho, double *gauss, void *stream);
 
+/* Allocation-free diagnostics, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the values pic_diagnostics gives on its first call,
+ * out[0..5] = U_E, U_B, K, Q, max |rho|, max |div E - rho|, with out[6] and
+ * out[7] NaN (no history is kept), synchronising.  Its partial sums, result
+ * and charge grid live in a fixed device array of the library (one copy per
+ * GPU, held from library load to process exit), so it needs no workspace and
+ * calls no allocating routine; grids above PIC_NOALLOC_MAX_CELLS nodes are
+ * rejected with PIC_EINVAL.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Sticky device flags are not read (they live in
+ * the workspace; pic_check reports them).  PIC_ENAN for a non-finite energy
+ * or charge. */
+#define PIC_NOALLOC_MAX_CELLS (1LL << 22)
+pic_status pic_diagnostics_noalloc(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
+                                   double *out_host, void *stream);
+
 /* ---- Reverse mode (adjoint) of one step, for gradients of a loss of the
  * final fields through K steps (the discrete adjoint of steps 1-4 above).
  *

@@ -15,6 +15,7 @@ PIC_OK, PIC_EINVAL, PIC_ECFL, PIC_EHIP, PIC_ENOMEM, PIC_ECROSS, PIC_ENAN, PIC_ES
 PIC_FP32, PIC_FP64 = 0, 1
 PIC_ACC_AUTO, PIC_ACC_FP32, PIC_ACC_FP64, PIC_ACC_FIX64 = 0, 1, 2, 3
 PIC_NDIAG = 8
+PIC_NOALLOC_MAX_CELLS = 1 << 22
 PIC_NPHASE = 4
 PHASES = ("sort", "zero_current", "push_deposit", "yee")
 
@@ -122,6 +123,8 @@ def load(path: str = LIB_PATH):
         "pic_diagnostics": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), P(ctypes.c_double), ctypes.c_void_p]),
         "pic_charge_density": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+        "pic_diagnostics_noalloc": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), P(ctypes.c_double),
+                                         ctypes.c_void_p]),
         "pic_check": (st, [ctx, ctypes.c_void_p]),
         "pic_set_timing": (st, [ctx, ctypes.c_int32]),
         "pic_get_timing": (st, [ctx, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]),

@@ -493,6 +493,35 @@ pic_status pic_charge_density(pic_ctx *c, const pic_species *sp, int32_t nspecie
   return PIC_OK;
 }
 
+pic_status pic_diagnostics_noalloc(pic_ctx *c, const pic_species *sp, int32_t nspecies, const pic_fields *f,
+                                   double *out, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!out || nspecies < 0 || nspecies > pic::kMaxSpecies || (nspecies > 0 && !sp))
+    return fail(c, PIC_EINVAL, "bad diagnostics arguments");
+  if (c->ncells > pic::kScratchCells)
+    return fail(c, PIC_EINVAL, "grid larger than PIC_NOALLOC_MAX_CELLS nodes: use pic_diagnostics with a workspace");
+  if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
+  for (int i = 0; i < nspecies; ++i)
+    if (!species_ok(c, &sp[i], false)) return fail(c, PIC_EINVAL, "bad species");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *scratch = nullptr;
+  hipError_t e = pic::scratch_address(&scratch);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics_noalloc: scratch address");
+  e = pic::launch_diagnostics_noalloc(*c, sp, nspecies, *f, scratch, s);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics_noalloc");
+  double res[PIC_NDIAG];
+  e = hipMemcpyAsync(res, scratch + pic::scratch_result_offset(), sizeof(double) * PIC_NDIAG, hipMemcpyDeviceToHost,
+                     s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "diagnostics_noalloc readback");
+  res[6] = NAN;
+  res[7] = NAN;
+  for (int i = 0; i < PIC_NDIAG; ++i) out[i] = res[i];
+  for (int i = 0; i < 4; ++i)
+    if (!std::isfinite(res[i])) return fail(c, PIC_ENAN, "non-finite energy or charge");
+  return PIC_OK;
+}
+
 pic_status pic_energy_adjoint(pic_ctx *c, const pic_fields *f, pic_fields *lam, double scale, void *stream) {
   if (!c) return PIC_EINVAL;
   if (c->p.open_x) return fail(c, PIC_EINVAL, "the adjoint covers periodic boxes only");

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "particle_math.h"
 #include "pic_internal.h"
@@ -388,6 +389,15 @@ hipError_t density(const pic_ctx &c, const pic_species *sp, int nsp, const pic_f
     }                                                                                 \
   } while (0)
 
+// Scratch of the allocation-free diagnostics (pic_diagnostics_noalloc): the
+// partial sums, the result and a charge grid of at most kScratchCells nodes,
+// one copy per GPU, held from module load to process exit.  In host code the
+// symbol's name is not a device address; hipGetSymbolAddress gives each
+// device's own copy, and only that address is ever passed to a kernel.
+constexpr size_t kScratchPartials = static_cast<size_t>(kDiagSlots) * kStride;
+constexpr size_t kScratchResult = 16;
+static __device__ __align__(256) double scratch[kScratchPartials + kScratchResult + kScratchCells];
+
 }  // namespace
 
 hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
@@ -401,5 +411,35 @@ hipError_t launch_charge_density(const pic_ctx &c, const pic_species *sp, int ns
                                  double *rho, double *gauss, hipStream_t s) {
   PIC_DIAG_DISPATCH(density, c, sp, nspecies, f, rho, gauss, s);
 }
+
+hipError_t scratch_address(double **out) {
+  // one address per device, looked up once with that device current
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<double *>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+hipError_t launch_diagnostics_noalloc(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
+                                      double *scratch_ptr, hipStream_t s) {
+  if (c.ncells > kScratchCells) return hipErrorInvalidValue;
+  DiagBufs b{scratch_ptr, scratch_ptr + kScratchPartials + kScratchResult, nullptr, nullptr,
+             scratch_ptr + kScratchPartials, false, false, false};
+  PIC_DIAG_DISPATCH(run, c, sp, nspecies, f, b, s);
+}
+
+size_t scratch_result_offset() { return kScratchPartials; }
 
 }  // namespace pic

@@ -18,6 +18,10 @@ constexpr int kMaxSpecies = 8;         // species per diagnostics call
 constexpr int kMaxSortLevels = 128;    // largest pic_params.sort_levels
 constexpr int kDiagBlocks = 1024;      // partial sums per species / per grid pass
 constexpr int kDiagSlots = PIC_NDIAG;  // UE UB K Q max|rho| max|G| max|dG| max|cont|
+// Largest grid (nodes) of the allocation-free diagnostics, whose charge grid
+// lives in a fixed device array, and the devices it keeps an address for.
+constexpr int64_t kScratchCells = PIC_NOALLOC_MAX_CELLS;
+constexpr int kMaxDevices = 64;
 // Largest capacity of the fused kernel's list of particles that need the
 // wide Esirkepov window (their nearest node changed), per precision; the
 // context lowers it to what the LDS left by the field and current boxes holds.
@@ -161,6 +165,13 @@ hipError_t launch_diagnostics(const pic_ctx &c, const pic_species *sp, int nspec
 // rho (and, when gauss is not null, div E - rho) into caller-owned FP64 grids.
 hipError_t launch_charge_density(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields *f,
                                  double *rho, double *gauss, hipStream_t s);
-
+// The device address of this device's copy of the allocation-free
+// diagnostics' scratch array (looked up once per device).
+hipError_t scratch_address(double **out);
+// Diagnostics without history into that scratch; the result's 8 doubles sit
+// at scratch_result_offset() doubles from its start.
+hipError_t launch_diagnostics_noalloc(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
+                                      double *scratch, hipStream_t s);
+size_t scratch_result_offset();
 
 }  // namespace pic
