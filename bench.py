@@ -22,7 +22,9 @@ Also printed, in the same JSON line:
   same workload, with the host's core count and CPU model;
 * fp64: the same step in FP64 (value and roofline);
 * adjoint: forward and backward time of the differentiable 2D rollout;
-* laser_foil: time per step of the two laser-on-foil boxes (FP32).
+* laser_foil: time per step of the two laser-on-foil boxes (FP32), once the
+  laser has reached the foil;
+* two_stream: the paper's scaling workload at its full size (1.81 G particles).
 """
 from __future__ import annotations
 
@@ -37,6 +39,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LDS_CURRENT = "auto"  # accumulator of the fused kernel's on-chip current (FP32 state), set by --lds-current
 
 
 def particle_bytes(prec: str, dims: int) -> int:
@@ -118,7 +121,8 @@ def build_sim(w, prec: str, scale_note: str = ""):
     from paper_1503_02464_amd.configs import BENCH_LAUNCH
     lc = BENCH_LAUNCH[prec]
     sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, prec, tile=lc["tile"], slack=lc["slack"],
-                     sort_every=lc["sort_every"], max_particles=sp["w"].shape[0])
+                     sort_every=lc["sort_every"], max_particles=sp["w"].shape[0],
+                     current_accum=LDS_CURRENT if prec == "fp32" else "auto")
     h = sim.add_species(sp)
     del sp
     # Set-up: the first sort bins the generator's cell-by-cell order into
@@ -176,6 +180,7 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
     sim.step(steps)
     tim = sim.get_timing()
     sim.set_timing(False)
+    timed_sorts = sorts_in(sim, steps)  # the sort steps among the event-timed ones
     diag = sim.diagnostics()
     sim.close()
     push_ms, push_n = tim["push_deposit"]
@@ -183,8 +188,13 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
     sort_ms, sort_n = tim["sort"]
     zero_ms, zero_n = tim["zero_current"]
     per_launch_bytes = npart * particle_bytes(prec, w.dims) + w.ncells * cell_bytes(prec)
+    # In 3D a sort step's push also takes over the sort's copy: it reads each
+    # particle's source index and writes its weight into the second set.
+    folded = timed_sorts if w.dims == 3 else 0
+    folded_bytes = per_launch_bytes + npart * (4 + (4 if prec == "fp32" else 8))
+    timed_bytes = (push_n - folded) * per_launch_bytes + folded * folded_bytes
     push_avg_s = push_ms / max(push_n, 1) / 1e3
-    achieved = per_launch_bytes / push_avg_s / 1e9
+    achieved = timed_bytes / (push_ms / 1e3) / 1e9
     yee_avg_s = yee_ms / max(yee_n, 1) / 1e3
     return {
         "value": npart * steps / elapsed,
@@ -205,6 +215,8 @@ def run_precision(w, prec: str, steps: int, warmup: int) -> dict:
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(w, prec),
             "bytes_per_launch": per_launch_bytes,
+            "bytes_per_folded_launch": folded_bytes,
+            "launches": {"in_place": push_n - folded, "folded": folded},
             "binding": measured_binding(w, prec),
         },
         "yee_cell_updates_per_s": w.ncells / yee_avg_s,
@@ -247,11 +259,20 @@ def adjoint_timing(prec: str = "fp32") -> dict:
             "grad_norm_src": float(s.grad.norm().item()), "grad_norm_u0": float(u0.grad.norm().item())}
 
 
+def pulse_at_foil_steps(w) -> int:
+    """Steps until the laser's peak reaches the foil's front surface: the
+    envelope peaks at t0 on the sheet, which is (foil_x0 - plane) dx from the
+    foil, travelled at c = 1."""
+    import math
+    return int(math.ceil((w.t0 + (w.foil_x[0] - w.laser_plane) * w.dx[0]) / w.dt))
+
+
 def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     """A laser-on-foil box (open x faces, laser sheet, electrons + ions) in its
-    launch configuration, FP32: time per whole step and pushes per second of
-    both species.  Most tiles hold no particle, so this measures how little
-    the empty ones cost."""
+    launch configuration, FP32, timed over `steps` steps that start once the
+    laser's peak has reached the foil (the run first steps there): time per
+    whole step and pushes per second of the particles still live, with the
+    live and straggler counts at the end."""
     import torch
 
     from paper_1503_02464_amd.sim import Simulation
@@ -260,13 +281,83 @@ def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     e, i = w.species()
     npart = e["w"].shape[0] + i["w"].shape[0]
     sim = Simulation(w.dims, w.n, w.dx, w.dt, w.order, "fp32", tile=w.tile, slack=1, sort_every=LASER_SORT_EVERY,
-                     max_particles=e["w"].shape[0], open_x=True, absorb=w.absorb, sort_levels=w.sort_levels)
+                     max_particles=e["w"].shape[0], open_x=True, absorb=w.absorb, sort_levels=w.sort_levels,
+                     current_accum=LDS_CURRENT)
     sim.set_laser(**w.laser())
-    for h in (sim.add_species(e), sim.add_species(i)):
+    hs = [sim.add_species(e), sim.add_species(i)]
+    for h in hs:
         sim.sort(h)  # tiles and levels, then node order (as in build_sim)
         sim.sort(h)
     del e, i
     log(f"{w.name}: set up {npart} particles in {time.time() - t0:.1f}s")
+    reach = pulse_at_foil_steps(w)
+    t1 = time.time()
+    sim.step(max(reach, warmup) + to_sort_step(sim, max(reach, warmup)))
+    torch.cuda.synchronize()
+    sim.check()
+    log(f"{w.name}: stepped to {sim.step_count} (pulse peak at the foil after {reach}) in {time.time() - t1:.1f}s")
+    live0 = sum(int(sim.live(h).sum().item()) for h in hs)
+    t2 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t2
+    sim.check()
+    strays = sim.straggler_count()
+    live1 = sum(int(sim.live(h).sum().item()) for h in hs)
+    sorts = sorts_in(sim, steps)
+    sim.set_timing(True)
+    sim.step(steps)
+    tim = sim.get_timing()
+    sim.set_timing(False)
+    diag = sim.diagnostics()
+    sim.close()
+    return {"workload": w.name, "particles": npart, "cells": w.ncells, "steps": steps,
+            "timed_from_step": reach, "pulse_peak_at_foil_step": reach,
+            "sort_every": LASER_SORT_EVERY, "sorts_in_timed_steps": sorts,
+            "live_particles": {"start": live0, "end": live1, "removed_before": npart - live0},
+            "stragglers_last_launch": strays,
+            "ms_per_step": el / steps * 1e3, "pushes_per_s": 0.5 * (live0 + live1) * steps / el,
+            "phases_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in tim.items()},
+            "energy": {k: diag[k] for k in ("UE", "UB", "K")}}
+
+
+def two_stream_timing(steps: int, warmup: int, scale: int = 1) -> dict:
+    """The paper's scaling workload (Sec. 4) at its full size on one GPU: two
+    counter-streaming electron beams, 512x512x128 cells, 27 particles per cell
+    per beam (1.81 G particles, about 58 GB per particle set in FP32), drawn
+    on the device; FP32, quadratic shape.  Time per step, pushes per second
+    and the fused kernel's HBM fraction."""
+    import torch
+
+    from paper_1503_02464_amd import inputs
+    from paper_1503_02464_amd.configs import two_stream_3d
+    from paper_1503_02464_amd.sim import Simulation
+
+    w = two_stream_3d(scale)
+    ppb = w.ppc // 2
+    npb = w.ncells * ppb
+    # two particle sets per beam (32 B per particle each), the workspace (32 B per particle of one beam)
+    need = 2 * 2 * npb * 32 + npb * 32 + 16 * w.ncells * 4
+    free, total = torch.cuda.mem_get_info()
+    if need > 0.95 * free:
+        log(f"{w.name}: needs {need / 2**30:.0f} GiB, {free / 2**30:.0f} GiB free: skipped")
+        return {"workload": w.name, "skipped": "not enough device memory"}
+    t0 = time.time()
+    sim = Simulation(3, w.n, w.dx, w.dt, w.order, "fp32", tile=w.tile, slack=1, sort_every=12, max_particles=npb,
+                     sort_levels=w.extra["sort_levels"], current_accum=LDS_CURRENT)
+    hs = []
+    for b, sign in enumerate((1.0, -1.0)):
+        h = sim.new_species(-1.0, 1.0, npb)
+        inputs.uniform_plasma_device(h.sets[0], w.n, 3, sim.bits, ppb, (sign * w.extra["u0"], 0.0, 0.0), w.u_sigma,
+                                     w.weight, w.seed + b)
+        hs.append(h)
+    torch.cuda.synchronize()
+    for h in hs:
+        sim.sort(h)
+        sim.sort(h)
+    torch.cuda.synchronize()
+    log(f"{w.name}: {2 * npb} particles drawn and sorted in {time.time() - t0:.1f}s, "
+        f"{torch.cuda.memory_allocated() / 2**30:.0f} GiB allocated")
     sim.step(warmup + to_sort_step(sim, warmup))
     torch.cuda.synchronize()
     sim.check()
@@ -280,11 +371,25 @@ def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     sim.step(steps)
     tim = sim.get_timing()
     sim.set_timing(False)
+    timed_sorts = sorts_in(sim, steps)
+    strays = sim.straggler_count()
+    diag = sim.diagnostics()
     sim.close()
-    return {"workload": w.name, "particles": npart, "cells": w.ncells, "steps": steps,
-            "sort_every": LASER_SORT_EVERY, "sorts_in_timed_steps": sorts,
-            "ms_per_step": el / steps * 1e3, "pushes_per_s": npart * steps / el,
-            "phases_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in tim.items()}}
+    push_ms, push_n = tim["push_deposit"]
+    per_launch = npb * particle_bytes("fp32", 3) + w.ncells * cell_bytes("fp32")
+    folded = 2 * timed_sorts
+    timed_bytes = (push_n - folded) * per_launch + folded * (per_launch + npb * 8)
+    achieved = timed_bytes / (push_ms / 1e3) / 1e9
+    log(f"{w.name}: {el / steps * 1e3:.1f} ms per step")
+    return {"workload": w.name, "particles": 2 * npb, "cells": w.ncells, "steps": steps,
+            "sort_every": 12, "sorts_in_timed_steps": sorts, "ms_per_step": el / steps * 1e3,
+            "pushes_per_s": 2 * npb * steps / el,
+            "phases_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in tim.items()},
+            "push_deposit_roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                      "bytes_per_launch": per_launch},
+            "stragglers_last_launch": strays, "energy": {k: diag[k] for k in ("UE", "UB", "K")},
+            "data": "drawn on the device (torch's seeded generator)"}
 
 
 def copy_probe(nbytes: int = 1 << 30) -> None:
@@ -370,7 +475,12 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-laser", action="store_true", help="skip the two laser-on-foil boxes")
+    ap.add_argument("--no-two-stream", action="store_true", help="skip the two-stream box (1.81 G particles)")
+    ap.add_argument("--lds-current", default="auto", choices=["auto", "fix64", "fp64", "fp32"],
+                    help="accumulator of the fused kernel's on-chip current for the FP32 state")
     args = ap.parse_args()
+    global LDS_CURRENT
+    LDS_CURRENT = args.lds_current
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU spatial decomposition "
               "is not implemented", file=sys.stderr)
@@ -388,6 +498,9 @@ def main() -> int:
     if not args.no_laser and args.scale == 1:
         from paper_1503_02464_amd.configs import laser_foil_2d, laser_foil_3d
         laser = [laser_foil_timing(wl, args.steps, args.warmup) for wl in (laser_foil_2d(), laser_foil_3d())]
+    two = None
+    if not args.no_two_stream and args.scale == 1:
+        two = two_stream_timing(args.steps, args.warmup)
     if args.copy_probe:
         copy_probe()
     base = None if args.no_cpu_baseline else cpu_baseline(w)
@@ -407,7 +520,8 @@ def main() -> int:
         "config": {"workload": w.name, "cells": list(w.n), "particles": res32["particles"], "ppc": w.ppc,
                    "shape_order": w.order, "dx": w.dx[0], "dt": w.dt, "u_sigma": w.u_sigma,
                    **{k: (list(v) if isinstance(v, tuple) else v) for k, v in BENCH_LAUNCH["fp32"].items()},
-                   "positions": "int32 cell + f32 offset", "lds_current": "f64"},
+                   "positions": "int32 cell + f32 offset",
+                   "lds_current": "fixed point, 64-bit" if args.lds_current in ("auto", "fix64") else args.lds_current},
         "roofline": res32["roofline"],
         "cpu_baseline": base,
         "phases_ms_per_launch": res32["phases_ms_per_launch"],
@@ -419,6 +533,7 @@ def main() -> int:
                                                                   "sorts_in_timed_steps", "yee_cell_updates_per_s")},
         "adjoint": adj,
         "laser_foil": laser,
+        "two_stream": two,
         # error bounds against the FP64 CPU oracle that the GPU parity tests
         # enforce on this path (one step from an FP32-representable state for
         # FP32; every quantity for FP64), including at this workload's full size

@@ -116,10 +116,12 @@ typedef struct {
      * 377) and y, z stay periodic; a particle whose x cell leaves
      * [absorb, n[0] - absorb) after a move deposits that move's current and
      * is then removed: its weight becomes 0, the fused step skips it, and
-     * the next sort moves it behind every tile and drops it: pic_sort and
-     * pic_step then set the species' np to tile_start[ntiles], the live count
-     * (reading it back synchronises the stream once per sort).  Weight-0
-     * particles are always inert when open_x = 1. */
+     * the next sort moves it behind every tile.  pic_sort then sets the
+     * species' np to tile_start[ntiles], the live count (reading it back
+     * synchronises the stream); pic_step copies that count to pinned host
+     * memory without waiting and drops the removed particles at the
+     * species' next sort in a later call or step, once the count has
+     * arrived.  Weight-0 particles are always inert when open_x = 1. */
     int32_t open_x;
     int32_t absorb;        /* cells between each x face and the particle region, >= 2 shape_order + 2,
                               and n[0] >= 2 absorb + 2 (open_x only) */

@@ -286,6 +286,9 @@ void pic_destroy(pic_ctx *c) {
     hipEventDestroy(ev.b);
   }
   for (auto e : c->spare) hipEventDestroy(e);
+  for (auto e : c->live_event)
+    if (e) hipEventDestroy(e);
+  if (c->live_host) hipHostFree(c->live_host);
   delete c;
 }
 
@@ -432,7 +435,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
       const int64_t np_src = sp[i].np;  // a sort with open faces drops removed particles from np
       if (cadence || !sp[i].sorted) {
         PhaseTimer t(c, s, pic::kPhaseSort);
-        e = pic::launch_sort(*c, sp[i], s, fold ? &src : nullptr);
+        e = pic::launch_sort(*c, sp[i], s, fold ? &src : nullptr, false);
         if (e != hipSuccess) return hip_fail(c, e, "sort");
       }
       if (sp[i].np == 0) continue;

@@ -383,19 +383,21 @@ __device__ __forceinline__ void deposit(const Acc &acc, const int c0[3], const T
 
 // One addition into an on-chip current accumulator of type S.  Floating
 // accumulators add the value; the 64-bit fixed-point one (unsigned long long,
-// two's complement) adds v 2^shift rounded to the nearest integer, where
-// shift keeps every contribution of the launch within 2^30.
+// two's complement) adds v rounded to the nearest integer: its callers pass
+// contributions already scaled by 2^shift (the coefficients of the current
+// carry the factor), which keeps every one within 2^30.
 template <typename S, typename V>
-__device__ __forceinline__ void lds_add(S *p, V v, int) {
+__device__ __forceinline__ void lds_add(S *p, V v) {
   atomicAdd(p, static_cast<S>(v));
 }
 template <typename V>
-__device__ __forceinline__ void lds_add(unsigned long long *p, V v, int shift) {
-  const int k = static_cast<int>(rintf(ldexpf(static_cast<float>(v), shift)));
+__device__ __forceinline__ void lds_add(unsigned long long *p, V v) {
+  const int k = static_cast<int>(rintf(static_cast<float>(v)));
   atomicAdd(p, static_cast<unsigned long long>(static_cast<long long>(k)));
 }
 
-// The value an accumulator holds, in the state's type T.
+// The value an accumulator holds, in the state's type T (the fixed-point sum
+// scaled back by 2^-shift).
 template <typename T, typename S>
 __device__ __forceinline__ T lds_value(S a, int) {
   return static_cast<T>(a);
@@ -447,13 +449,12 @@ struct LdsFields {
 template <typename S, int SX, int SXY, int VOL, int OX, int OY, int OZ>
 struct LdsBox {
   S *base;
-  int shift;  // fixed-point accumulators only
   __device__ __forceinline__ S load(int comp, int i, int j, int k) const {
     return base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)];
   }
   template <typename V>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
-    lds_add(&base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)], v, shift);
+    lds_add(&base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)], v);
   }
 };
 
@@ -461,10 +462,9 @@ template <typename S>
 struct LdsCurrent {
   S *base;
   int sx, sxy, vol, o0, o1, o2;
-  int shift;
   template <typename V>
   __device__ __forceinline__ void add(int comp, int i, int j, int k, V v) const {
-    lds_add(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], v, shift);
+    lds_add(&base[comp * vol + (i - o0) + sx * (j - o1) + sxy * (k - o2)], v);
   }
 };
 

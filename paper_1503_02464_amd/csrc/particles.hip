@@ -102,8 +102,7 @@ __device__ __forceinline__ double lane_push(int to, double v) {
 // through per-lane strides.
 template <typename T, int M, typename S>
 __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jvol, int jlo, const int c0[3],
-                                                  const T o0[3], const int dc[3], const T o1[3], const T jc[3],
-                                                  int shift) {
+                                                  const T o0[3], const int dc[3], const T o1[3], const T jc[3]) {
   constexpr int WN = M + 1, WW = M + 2;  // narrow and wide node counts
   bool cr[3];
 #pragma unroll
@@ -149,7 +148,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
           const T t = e.A[1][j] * e.S0[2][k] + e.Bf[1][j] * e.DS[2][k];
 #pragma unroll
           for (int i = 0; i < WW - 1; ++i)
-            lds_add(&jl[cb[0] + org + i * st[0] + j * st[1] + k * st[2]], -pc[0] * e.CDS[0][i] * t, shift);
+            lds_add(&jl[cb[0] + org + i * st[0] + j * st[1] + k * st[2]], -pc[0] * e.CDS[0][i] * t);
         }
   // along the second axis
 #pragma unroll
@@ -161,7 +160,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 #pragma unroll
         for (int j = 0; j < WW - 1; ++j)
           if (j < WN - 1 || wide[1])
-            lds_add(&jl[cb[1] + org + i * st[0] + j * st[1] + k * st[2]], -pc[1] * e.CDS[1][j] * t, shift);
+            lds_add(&jl[cb[1] + org + i * st[0] + j * st[1] + k * st[2]], -pc[1] * e.CDS[1][j] * t);
       }
   // along the third axis
 #pragma unroll
@@ -173,7 +172,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 #pragma unroll
         for (int k = 0; k < WW - 1; ++k)
           if (k < WN - 1 || wide[2])
-            lds_add(&jl[cb[2] + org + i * st[0] + j * st[1] + k * st[2]], -pc[2] * e.CDS[2][k] * t, shift);
+            lds_add(&jl[cb[2] + org + i * st[0] + j * st[1] + k * st[2]], -pc[2] * e.CDS[2][k] * t);
       }
 }
 
@@ -184,7 +183,7 @@ __device__ __forceinline__ void esirkepov_rotated(S *jl, int jx, int jxy, int jv
 template <typename T, int M, typename S>
 __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, int jlo, const int c0[3],
                                                      const T o0[3], const int dc[3], const T o1[3], const T jc[3],
-                                                     T jzc, int shift) {
+                                                     T jzc) {
   constexpr int WN = M + 1, WW = M + 2;
   bool cr[2];
 #pragma unroll
@@ -214,7 +213,7 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
       const T t = e.A[1][j];
 #pragma unroll
       for (int i = 0; i < WW - 1; ++i)
-        lds_add(&jl[cb[0] + org + i * st[0] + j * st[1]], -pc[0] * e.CDS[0][i] * t, shift);
+        lds_add(&jl[cb[0] + org + i * st[0] + j * st[1]], -pc[0] * e.CDS[0][i] * t);
     }
   // along the other in-plane axis
 #pragma unroll
@@ -223,7 +222,7 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
 #pragma unroll
     for (int j = 0; j < WW - 1; ++j)
       if (j < WN - 1 || wide1)
-        lds_add(&jl[cb[1] + org + i * st[0] + j * st[1]], -pc[1] * e.CDS[1][j] * t, shift);
+        lds_add(&jl[cb[1] + org + i * st[0] + j * st[1]], -pc[1] * e.CDS[1][j] * t);
   }
   // out of the plane
   if (jzc != T(0))
@@ -232,8 +231,7 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
       if (j < WN || wide1)
 #pragma unroll
         for (int i = 0; i < WW; ++i)
-          lds_add(&jl[2 * jvol + org + i * st[0] + j * st[1]], jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j]),
-                  shift);
+          lds_add(&jl[2 * jvol + org + i * st[0] + j * st[1]], jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j]));
 }
 
 template <typename T, int D>
@@ -357,6 +355,9 @@ struct TileArgs {
   int cross_cap;           // entries of the LDS list of wide-window particles
 };
 
+__device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); }
+
 // The power-of-two shift of a tile's fixed-point current: every contribution
 // is bounded by max_d |jc_d| w_max (2D J_z: |jz| w_max, since |v_z| < 1),
 // w_max the largest |w| among the tile's particles, and the shift brings that
@@ -403,13 +404,13 @@ template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
 struct FieldBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
   using G = FixedGeom<D, M, LX, LY, LZ, SL>;
   using type = LdsBox<T, G::FX, G::FX * G::FY, G::FVOL, G::FLO, G::FLO, D == 3 ? G::FLO : 0>;
-  __device__ static type make(T *base, const G &) { return type{base, 0}; }
+  __device__ static type make(T *base, const G &) { return type{base}; }
 };
 template <typename T, int D, int M, int LX, int LY, int LZ, int SL, int DD>
 struct CurrentBox<T, FixedGeom<D, M, LX, LY, LZ, SL>, DD> {
   using G = FixedGeom<D, M, LX, LY, LZ, SL>;
   using type = LdsBox<T, G::JX, G::JXY, G::JVOL, G::JLO, G::JLO, D == 3 ? G::JLO : 0>;
-  __device__ static type make(T *base, const G &, int shift) { return type{base, shift}; }
+  __device__ static type make(T *base, const G &) { return type{base}; }
 };
 template <typename T, int DD>
 struct FieldBox<T, RuntimeGeom, DD> {
@@ -421,8 +422,8 @@ struct FieldBox<T, RuntimeGeom, DD> {
 template <typename T, int DD>
 struct CurrentBox<T, RuntimeGeom, DD> {
   using type = LdsCurrent<T>;
-  __device__ static type make(T *base, const RuntimeGeom &g, int shift) {
-    return type{base, g.JX, g.JXY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0, shift};
+  __device__ static type make(T *base, const RuntimeGeom &g) {
+    return type{base, g.JX, g.JXY, g.JVOL, -g.JLO, -g.JLO, DD == 3 ? -g.JLO : 0};
   }
 };
 
@@ -548,10 +549,13 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     }
     __syncthreads();
     const int shift = kFixed ? fixed_shift<T>(s, __uint_as_float(*wbits), D) : 0;
+    // the current's coefficients, in the fixed-point box's units (2^shift)
+    const T tjc[3] = {scale2(s.jc[0], shift), scale2(s.jc[1], shift), scale2(s.jc[2], shift)};
+    const T tjz = scale2(s.jz, shift);
 
     // local frames: the tile origin is (0,0,0)
     const auto lf = FieldBox<T, G, D>::make(fl, geo);
-    const auto lj = CurrentBox<TJ, G, D>::make(jl, geo, shift);
+    const auto lj = CurrentBox<TJ, G, D>::make(jl, geo);
     const int lane = __lane_id();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -639,7 +643,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
         if (!ok) atomicOr(&flags[0], kFlagCross);
-        jz = D == 2 ? s.jz * u[2] * ig : T(0);
+        jz = D == 2 ? tjz * u[2] * ig : T(0);
         wide = ok && crosses<T, D, M>(o, dc, on);
         fast = ok && !wide;
       }
@@ -691,14 +695,14 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           unpack_local(sk, slc, sdc);
           Esirk<T, M> e;
           esirkepov_factors<T, D, M>(so, sdc, sn, e);
-          const T jc[3] = {sw * s.jc[0], sw * s.jc[1], sw * s.jc[2]};
+          const T jc[3] = {sw * tjc[0], sw * tjc[1], sw * tjc[2]};
           esirkepov_accumulate<T, D, M, true>(lj, slc, e, jc, T(0));
         }
       } else {
         if (fast) {
           Esirk<T, M> e;
           esirkepov_factors<T, D, M>(o, dc, on, e);
-          const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+          const T jc[3] = {w * tjc[0], w * tjc[1], w * tjc[2]};
           esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
         }
       }
@@ -723,7 +727,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           } else {  // list full: deposit here
             Esirk<T, M> e;
             esirkepov_factors<T, D, M>(o, dc, on, e);
-            const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+            const T jc[3] = {w * tjc[0], w * tjc[1], w * tjc[2]};
             esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * jz);
           }
         }
@@ -764,11 +768,11 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       }
       unpack_local(xk[k], lc, dc);
       const T w = xw[k];
-      const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+      const T jc[3] = {w * tjc[0], w * tjc[1], w * tjc[2]};
       if constexpr (D == 3)
-        esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, shift);
+        esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc);
       else
-        esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, w * xw[CAP + k], shift);
+        esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o0, dc, o1, jc, w * xw[CAP + k]);
     }
     __syncthreads();
 

@@ -93,6 +93,12 @@ struct pic_ctx {
   // (at most kMaxSpecies; entry i owns bucket-start slot i of the workspace):
   // the next sort of that species ranks by the runs tile_start describes
   std::vector<std::pair<const int32_t *, int64_t>> sorted_runs;
+  // Open x faces: each sort's live count (tile_start[ntiles]) of species slot
+  // i, copied to pinned host memory without waiting; the next sort of that
+  // species drops the removed particles once the copy's event has completed.
+  int32_t *live_host = nullptr;  // pinned, kMaxSpecies entries (allocated on first use)
+  hipEvent_t live_event[pic::kMaxSpecies] = {};
+  bool live_pending[pic::kMaxSpecies] = {};
   bool has_laser = false;
   pic_laser laser{};
   double laser_j0 = 0.0;  // sheet amplitude radiating laser.e0 on the lattice
@@ -152,7 +158,12 @@ hipError_t launch_particle_adjoint(const pic_ctx &c, const pic_species &sp, cons
                                    const pic_fields &lam, const pic_species_adjoint &lsp, hipStream_t s);
 // fold_src: when not null, the copy into the second set is left to the next
 // fused push (*fold_src receives the slots; null if the sort copied anyway).
-hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src = nullptr);
+// With open x faces, wait = true drops the removed particles from np at once
+// (synchronising); wait = false drops those of the previous sort of this
+// species if its live count has reached the host, and starts the copy of
+// this sort's count.
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src = nullptr,
+                       bool wait = true);
 void swap_sets(pic_species &sp);
 // The non-empty tiles of a species' last sort (list, count at [ntiles]), or
 // null when this context has not sorted that species.

@@ -623,7 +623,7 @@ void swap_sets(pic_species &sp) {
 int64_t sort_scan_blocks(int64_t nbuckets) { return (nbuckets + kScanTile - 1) / kScanTile; }
 int64_t sort_scan_capacity() { return static_cast<int64_t>(kScanBlock) * kScanItems; }
 
-hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src) {
+hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t **fold_src, bool wait) {
   // buckets: (tile, level) for every tile, then one for removed particles
   const int64_t nb = c.ntiles * c.levels + 1;
   int32_t *stay = c.wsp<int32_t>(c.ws.stay_count);
@@ -641,6 +641,24 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
       slot = static_cast<int>(i);
       by_runs = c.sorted_runs[i].second == sp.np && sp.sorted;
     }
+  if (slot >= 0 && c.live_pending[slot]) {
+    // The previous sort left the removed particles behind its tiles, from
+    // its live count on; pushes since then kept that order.  Drop them if the
+    // count has arrived (never wait for it) and the species is still that
+    // sort's particle set.
+    const hipError_t q = hipEventQuery(c.live_event[slot]);
+    if (q == hipSuccess) {
+      c.live_pending[slot] = false;
+      const int64_t nlive = c.live_host[slot];
+      if (by_runs && nlive >= 0 && nlive < sp.np) {
+        sp.np = nlive;
+        c.sorted_runs[slot].second = sp.np;
+      }
+    } else if (q != hipErrorNotReady) {
+      return q;
+    }
+    if (!by_runs) c.live_pending[slot] = false;
+  }
   if (slot < 0) {
     if (c.sorted_runs.size() < static_cast<size_t>(kMaxSpecies)) {
       slot = static_cast<int>(c.sorted_runs.size());
@@ -698,7 +716,7 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
     *fold_src = c.wsp<int32_t>(c.ws.sort_src);  // the caller's push copies, then swaps
   }
   sp.sorted = 1;
-  if (c.p.open_x && sp.np > 0) {
+  if (c.p.open_x && sp.np > 0 && wait) {
     // The removed particles now sit behind every tile, from tile_start[ntiles]
     // on: the species keeps only the live ones (a folded copy then never
     // reads the removed ones, and later sorts never rank them).
@@ -707,6 +725,24 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     if (nlive >= 0 && nlive < sp.np) sp.np = nlive;
+    c.live_pending[slot] = false;
+  } else if (c.p.open_x && sp.np > 0) {
+    // the live count goes to pinned host memory behind the sort; the next
+    // sort of this species applies it
+    if (!c.live_host) {
+      void *h = nullptr;
+      e = hipHostMalloc(&h, sizeof(int32_t) * kMaxSpecies, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      c.live_host = static_cast<int32_t *>(h);
+    }
+    if (!c.live_event[slot]) {
+      e = hipEventCreateWithFlags(&c.live_event[slot], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    e = hipMemcpyAsync(c.live_host + slot, sp.tile_start + c.ntiles, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(c.live_event[slot], s);
+    if (e != hipSuccess) return e;
+    c.live_pending[slot] = true;
   }
   c.sorted_runs[slot].second = sp.np;
   return hipSuccess;

@@ -159,3 +159,35 @@ def quiet_beams(n: tuple, dims: int, sub: tuple, u0: float, eps: float, k: float
         out.append({"q": float(q), "m": float(m), "cell": cell.copy(), "off": off.copy(), "u": u,
                     "w": np.full(npart, weight, np.float64)})
     return tuple(out)
+
+
+def uniform_plasma_device(arrays: dict, n: tuple, dims: int, bits: tuple, ppc: int, u_mean: tuple, u_sigma: float,
+                          weight: float, seed: int, chunk: int = 1 << 26) -> None:
+    """Fill device arrays (cell: packed int32, off[3], u[3], w; torch tensors)
+    in place with ``ppc`` particles per cell, cell by cell, offsets uniform in
+    [0,1), momenta Gaussian about u_mean, from torch's seeded device
+    generator, in chunks of ``chunk`` particles (for boxes too large to draw
+    on the host).  The draws differ from the numpy generators'; the layout is
+    the same."""
+    import torch
+    cell = arrays["cell"]
+    dev = cell.device
+    npart = int(n[0] * n[1] * n[2]) * ppc
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(int(seed))
+    for lo in range(0, npart, chunk):
+        hi = min(lo + chunk, npart)
+        lin = torch.arange(lo, hi, device=dev, dtype=torch.int64) // ppc
+        ix = lin % n[0]
+        iy = (lin // n[0]) % n[1]
+        iz = lin // (n[0] * n[1])
+        packed = ix | (iy << bits[0]) | (iz << (bits[0] + bits[1]))
+        cell[lo:hi] = packed.to(torch.int32)
+        del lin, ix, iy, iz, packed
+        for d in range(3):
+            off = arrays["off"][d]
+            if d < dims:
+                off[lo:hi] = torch.rand(hi - lo, generator=gen, device=dev, dtype=off.dtype)
+            u = arrays["u"][d]
+            u[lo:hi] = torch.randn(hi - lo, generator=gen, device=dev, dtype=u.dtype) * u_sigma + u_mean[d]
+        arrays["w"][lo:hi] = weight

@@ -219,6 +219,28 @@ class Simulation:
         self.species.append(state)
         return state
 
+    def new_species(self, q: float, m: float, npart: int) -> SpeciesState:
+        """A species of npart particles whose device arrays (state.sets[0], in
+        the packed-cell form) the caller fills, e.g. with a device-side
+        generator; the second set receives the sorts."""
+        dev, dt = self.device, self.dtype
+        cap = max(int(npart), 1)
+        sets = [{"cell": torch.zeros(cap, dtype=torch.int32, device=dev),
+                 "off": [torch.zeros(cap, dtype=dt, device=dev) for _ in range(3)],
+                 "u": [torch.zeros(cap, dtype=dt, device=dev) for _ in range(3)],
+                 "w": torch.zeros(cap, dtype=dt, device=dev)} for _ in range(2)]
+        tile_start = torch.zeros(self.ntiles + 1, dtype=torch.int32, device=dev)
+        st = L.Species()
+        st.np = int(npart)
+        st.q = float(q)
+        st.m = float(m)
+        self._fill_struct(st, sets[0], sets[1])
+        st.tile_start = _ptr(tile_start)
+        st.sorted = 0
+        state = SpeciesState(float(q), float(m), int(npart), sets, tile_start, st)
+        self.species.append(state)
+        return state
+
     @staticmethod
     def _fill_struct(st: L.Species, a: dict, b: dict) -> None:
         st.cell = _ptr(a["cell"])

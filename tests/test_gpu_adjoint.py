@@ -198,3 +198,35 @@ def test_fp32_rollout_gradient_against_fp64():
     assert cos(gs32, gs64) > 0.9999 and cos(gu32, gu64) > 0.9999
     r64.sim.close()
     r32.sim.close()
+
+
+@pytest.mark.parametrize("prec,steps", [("fp64", 24), ("fp32", 1)])
+def test_rollout_forward_instance_matches_oracle(prec, steps):
+    """The differentiable workload's own forward launch (2D, linear shape,
+    16x16 tiles, slack 2, one sort and no re-sort, the fixed-geometry instance
+    the rollout runs) against the FP64 oracle at 64^2 with 16 ppc and the E_y
+    source in place: FP64 to 1e-12 after 24 steps, FP32 to its one-step
+    tolerances from an FP32-exact state."""
+    import oracle as O
+    from gpu_helpers import compare_fields, compare_species, unique_weights
+    from paper_1503_02464_amd.sim import Simulation
+    w, g, sp, src = c5_like(64, 16, steps)
+    sp = unique_weights(sp, 730, scale=w.density * w.cell_volume / 16)
+    f = O.new_fields(g)
+    f["E"][1] = src
+    if prec == "fp32":
+        sp = inputs.round_f32(sp)
+        f = inputs.round_fields_f32(f)
+    s = Simulation(2, g.n, g.dx, g.dt, 1, prec, tile=(16, 16), slack=2, sort_every=0,
+                   max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    ref = O.copy_species(sp)
+    ref_f = {k: v.copy() for k, v in f.items()}
+    for _ in range(steps):
+        s.step(1)
+        assert O.step(g, ref_f, [ref]) == 0
+    s.check()
+    compare_species(g, prec, s.get_species(h), ref, "rollout forward")
+    compare_fields(prec, s.get_fields(), ref_f, what="rollout forward")
+    s.close()

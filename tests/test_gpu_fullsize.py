@@ -76,17 +76,28 @@ def test_sampled_particles(run):
     assert np.max(np.abs(dx)) <= t["pos"], np.max(np.abs(dx))
 
 
+def box_origins(g, tile=8, count=64, seed=301):
+    """Origins of 4^3 boxes that straddle tile seams on every axis (from two
+    cells below a seam to one above), the periodic seam among them (lo = n - 2
+    on every axis for the first box), the rest at seeded seams."""
+    r = inputs.rng(seed)
+    out = [np.array([g.n[d] - 2 for d in range(3)])]
+    while len(out) < count:
+        out.append(np.array([(tile * int(r.integers(0, g.n[d] // tile)) - 2) % g.n[d] for d in range(3)]))
+    return out
+
+
 def test_current_in_sample_boxes(run):
-    """J^{3/2} inside four 4^3 boxes from every particle whose cell lies within
-    three cells of a box (the Esirkepov window reaches at most that far)."""
+    """J^{3/2} inside 64 boxes of 4^3 nodes, each straddling tile seams on all
+    three axes (one the periodic seam), from every particle whose cell lies
+    within three cells of a box (the Esirkepov window reaches at most that
+    far): the merged per-tile current boxes must add up across the seams."""
     sim, g = run["sim"], run["g"]
     st = run["state1"]
     cells = torch.stack([torch.as_tensor(c, device="cuda") for c in
                          unpack_cells(st["cell"].cpu().numpy(), sim.bits)]).long()
-    r = inputs.rng(301)
     Jgpu = run["f2"]["J"]
-    for b in range(4):
-        lo = r.integers(0, g.n[0], 3)
+    for b, lo in enumerate(box_origins(g)):
         sel = torch.ones(cells.shape[1], dtype=torch.bool, device="cuda")
         for d in range(3):
             rel = (cells[d] - int(lo[d]) + 3) % g.n[d]

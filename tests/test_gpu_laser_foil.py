@@ -148,3 +148,133 @@ def test_scaled_2d_foil_at_the_laser_fp64():
     compare_fields("fp64", s.get_fields(), ref_f, what="scaled laser foil")
     assert np.max(np.abs(ref_f["E"][1])) > 0.5 * w.a0  # the pulse is there
     s.close()
+
+
+def pulse_at_foil(w) -> int:
+    """Steps until the laser's peak reaches the foil's front surface (the
+    envelope peaks at t0 on the sheet, (foil_x0 - plane) dx from the foil)."""
+    return int(np.ceil((w.t0 + (w.foil_x[0] - w.laser_plane) * w.dx[0]) / w.dt))
+
+
+@pytest.fixture(scope="module", params=["2d", "3d"])
+def active(request):
+    """A full-size box stepped past the arrival of the laser's peak at the foil
+    (2D: 1501 steps, the peak arrives after 1438; 3D: 501 steps of its 500,
+    the peak after 700, when the pulse front has been driving the foil for
+    about 25 laser periods), then one step more that does not re-sort."""
+    w = laser_foil_2d() if request.param == "2d" else laser_foil_3d()
+    n_active = 1501 if request.param == "2d" else 501
+    assert n_active % 4 != 0  # the next step keeps the particle order (sorts every 4 steps)
+    e, i = w.species()
+    s = make(w, "fp32", e["w"].shape[0])
+    s.set_laser(**w.laser())
+    hs = [s.add_species(e), s.add_species(i)]
+    q0 = s.diagnostics()["Q"]
+    sizes = (e["w"].shape[0], i["w"].shape[0])
+    del e, i
+    s.step(n_active)
+    s.check()
+    f1 = s.get_fields()
+    st1 = []
+    for h in hs:
+        cur = h.current()
+        st1.append({"cell": cur["cell"][:h.np].clone(), "off": [t[:h.np].clone() for t in cur["off"]],
+                    "u": [t[:h.np].clone() for t in cur["u"]], "w": cur["w"][:h.np].clone()})
+    s.step(1)
+    s.check()
+    f2 = s.get_fields()
+    d2 = s.diagnostics()
+    yield dict(w=w, s=s, hs=hs, st1=st1, f1=f1, f2=f2, q0=q0, d2=d2, sizes=sizes, n=n_active)
+    s.close()
+
+
+def test_sampled_particles_active_phase(active):
+    """Sampled particles, live and removed, of the step after the laser has
+    driven the foil: live ones follow the oracle's gather, Boris and move
+    (and leave where it says), removed ones stay exactly as they were."""
+    w, s = active["w"], active["s"]
+    g = ora_grid(w)
+    t = TOL["fp32"]
+    hot = 0.0
+    for k, (h, q, m) in enumerate(zip(active["hs"], (-1.0, 1.0), (1.0, w.m_ion))):
+        n1 = active["st1"][k]["w"].shape[0]
+        idx = np.sort(inputs.rng(520 + k).choice(n1, min(8192, n1), replace=False))
+        before = host(s, active["st1"][k], idx, q, m)
+        cur = h.current()
+        after = host(s, {"cell": cur["cell"], "off": cur["off"], "u": cur["u"], "w": cur["w"]}, idx, q, m)
+        dead = before["w"] == 0
+        for key in ("cell", "off", "u", "w"):  # removed particles are inert
+            assert np.array_equal(after[key][..., dead], before[key][..., dead]), key
+        ref = O.copy_species(before)
+        EB = O.gather(g, active["f1"]["E"], active["f1"]["B"], ref["cell"], ref["off"])
+        ref["u"] = O.boris(q, m, g.dt, EB, ref["u"])
+        ref["cell"], ref["off"], _, bad = O.move(g, ref["u"], ref["cell"], ref["off"])
+        assert bad == 0
+        O.absorb(ref, w.absorb, w.n[0] - w.absorb)
+        live = ~dead
+        assert np.array_equal(after["w"][live], ref["w"][live])
+        du = np.max(np.abs(after["u"][:, live] - ref["u"][:, live])) / max(np.max(np.abs(ref["u"][:, live])), 1e-30)
+        n = np.array(g.n)[:, None]
+        dx = (after["cell"] + after["off"] - ref["cell"] - ref["off"] + n / 2) % n - n / 2
+        assert du <= t["u"], (k, du)
+        assert np.max(np.abs(dx[:, live])) <= t["pos"], (k, np.max(np.abs(dx[:, live])))
+        if k == 0:
+            hot = float(np.max(np.abs(before["u"][:, live])))
+    assert hot > 0.5, hot  # the sampled electrons include laser-driven relativistic ones
+
+
+def test_fields_everywhere_active_phase(active):
+    """E and B after the step from the state before it and the GPU's current
+    (particles and laser sheet) through the oracle's open-face Yee update,
+    with the pulse at the foil."""
+    g = ora_grid(active["w"])
+    f = {k: v.copy() for k, v in active["f1"].items()}
+    f["J"] = active["f2"]["J"].copy()
+    O.yee_step_open(g, f)
+    for k in ("E", "B"):
+        err = np.max(np.abs(active["f2"][k] - f[k])) / np.max(np.abs(f[k]))
+        assert err <= TOL["fp32"][k], (k, err)
+    assert np.max(np.abs(f["E"][1])) > 0.5 * active["w"].a0  # the pulse is in the box
+
+
+def test_charge_of_the_live_particles_active_phase(active):
+    """Electrons and ions carry equal weights, so the FP64 total charge is the
+    weight times (live ions - live electrons), removals included."""
+    w, s = active["w"], active["s"]
+    counts = [int(s.live(h).sum().item()) for h in active["hs"]]
+    assert counts[0] <= active["sizes"][0] and counts[1] <= active["sizes"][1]
+    want = w.weight * (counts[1] - counts[0])
+    assert abs(active["d2"]["Q"] - want) <= 1e-12 * w.weight * sum(counts), (active["d2"]["Q"], want, counts)
+
+
+def test_c2_fp64_full_run_conserves_charge_and_gauss():
+    """The 2D laser-foil workload at its full size and length in FP64 (2000
+    steps): every 200 steps, Gauss's residual div E - rho is unchanged (to
+    round-off) on the nodes away from the faces, the laser sheet and the
+    removal columns, and the charge matches the live particles.  The energy
+    of fields and particles is reported along the way."""
+    w = laser_foil_2d()
+    e, i = w.species()
+    s = make(w, "fp64", e["w"].shape[0])
+    s.set_laser(**w.laser())
+    hs = [s.add_species(e), s.add_species(i)]
+    del e, i
+    x = np.arange(w.ncells) % w.n[0]
+    interior = (x >= w.absorb + 3) & (x < w.n[0] - w.absorb - 3)
+    rho, G = s.charge_density(gauss=True)
+    scale = float(np.max(np.abs(s.charge_density([hs[0]]))))  # the electrons' density (the pair's rho is 0)
+    energy = []
+    for k in range(10):
+        s.step(200)
+        s.check()
+        rho1, G1 = s.charge_density(gauss=True)
+        dG = float(np.max(np.abs(G1 - G)[interior]))
+        assert dG <= 1e-12 * scale, (k, dG, scale)
+        d = s.diagnostics()
+        counts = [int(s.live(h).sum().item()) for h in hs]
+        assert abs(d["Q"] - w.weight * (counts[1] - counts[0])) <= 1e-12 * w.weight * sum(counts)
+        energy.append((s.step_count, d["UE"], d["UB"], d["K"], counts))
+        G = G1
+    print("laser-foil-2d FP64 energy (step, U_E, U_B, K, live):", energy)
+    assert energy[-1][3] > 0  # the foil has been heated
+    s.close()
