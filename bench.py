@@ -16,7 +16,9 @@ Also printed, in the same JSON line:
   FETCH_SIZE / WRITE_SIZE counters recorded under profiles/ (null once the
   kernel sources differ from the ones they were taken on); binding = the
   same record's SQ counters: the fractions of the kernel's cycles the LDS is
-  busy and replaying conflicts, and VALU issue (the kernel is LDS-bound);
+  busy and replaying conflicts, and VALU issue (the kernel is bound by LDS
+  and VALU work, not by HBM); copy_GBs = what a plain 4 GiB device copy
+  reaches on this GPU, the practical HBM roof beside the 8 TB/s peak;
 * cpu_baseline: the FP64 CPU oracle on the host: one thread on a 64^3 box
   and every core (the oracle's all-core timing build) on a 128^3 box of the
   same workload, with the host's core count and CPU model;
@@ -95,13 +97,18 @@ def measured_traffic(w, prec: str):
 
 def measured_binding(w, prec: str):
     """What binds the fused kernel, from its SQ counters (fractions of the
-    kernel's cycles per CU / SIMD), or None: the kernel is limited by LDS
-    throughput (its FP64 LDS current and the gather's LDS reads), not HBM."""
+    kernel's busy cycles: LDS unit active per CU, LDS bank-conflict replays,
+    VALU issue per SIMD), or None.  unit names the busiest of LDS and VALU
+    (both when they are within 0.05 of each other): the kernel is limited by
+    on-chip work (the current box's atomics, the gather's LDS reads and the
+    per-particle arithmetic), not by HBM."""
     prof = measured_profile(w, prec)
     if prof is None or "lds_active_frac" not in prof:
         return None
-    return {"unit": "LDS", "lds_active_frac": prof["lds_active_frac"],
-            "lds_bank_conflict_frac": prof["lds_bank_conflict_frac"], "valu_issue_frac": prof["valu_issue_frac"]}
+    lds, valu = prof["lds_active_frac"], prof["valu_issue_frac"]
+    unit = "LDS+VALU" if abs(lds - valu) < 0.05 else ("LDS" if lds > valu else "VALU")
+    return {"unit": unit, "lds_active_frac": lds, "lds_bank_conflict_frac": prof["lds_bank_conflict_frac"],
+            "valu_issue_frac": valu}
 
 
 def log(msg: str) -> None:
@@ -404,6 +411,26 @@ def copy_probe(nbytes: int = 1 << 30) -> None:
     log(f"copy probe: {nbytes} bytes read and written per copy")
 
 
+def copy_bandwidth(nbytes: int = 4 << 30, reps: int = 10) -> float:
+    """HBM bandwidth a plain device-to-device copy reaches on this GPU (bytes
+    read + written per second, GB/s): the practical roof beside the 8 TB/s
+    of the specification."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (t0.elapsed_time(t1) / 1e3) / 1e9
+    del a, b
+    log(f"copy bandwidth: {gbs:.0f} GB/s")
+    return gbs
+
+
 def host_facts() -> dict:
     """The host's cores (this process's CPU affinity), the thread count the
     all-core leg uses (OMP_NUM_THREADS when set, at most the affinity) and
@@ -491,6 +518,7 @@ def main() -> int:
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = thermal_3d(scale=args.scale)
+    copy_gbs = copy_bandwidth()
     res32 = run_precision(w, "fp32", args.steps, args.warmup)
     res64 = None if args.no_fp64 else run_precision(w, "fp64", args.steps, args.warmup)
     adj = None if (args.no_adjoint or args.scale != 1) else adjoint_timing("fp32")
@@ -522,7 +550,8 @@ def main() -> int:
                    **{k: (list(v) if isinstance(v, tuple) else v) for k, v in BENCH_LAUNCH["fp32"].items()},
                    "positions": "int32 cell + f32 offset",
                    "lds_current": "fixed point, 64-bit" if args.lds_current in ("auto", "fix64") else args.lds_current},
-        "roofline": res32["roofline"],
+        "roofline": dict(res32["roofline"], copy_GBs=round(copy_gbs, 1),
+                         frac_of_copy=round(res32["roofline"]["achieved"] / copy_gbs, 4)),
         "cpu_baseline": base,
         "phases_ms_per_launch": res32["phases_ms_per_launch"],
         "sorts_in_timed_steps": res32["sorts_in_timed_steps"],
