@@ -25,7 +25,8 @@ Also printed, in the same JSON line:
 * fp64: the same step in FP64 (value and roofline);
 * adjoint: forward and backward time of the differentiable 2D rollout;
 * laser_foil: time per step of the two laser-on-foil boxes (FP32), once the
-  laser has reached the foil;
+  laser has reached the foil, and with the output manager writing a field
+  plane, a density plane and an electron phase-space dump every 4 steps;
 * two_stream: the paper's scaling workload at its full size (1.81 G particles).
 """
 from __future__ import annotations
@@ -274,6 +275,65 @@ def pulse_at_foil_steps(w) -> int:
     return int(math.ceil((w.t0 + (w.foil_x[0] - w.laser_plane) * w.dx[0]) / w.dt))
 
 
+def laser_outputs(w, every: int) -> list:
+    """A laser-foil run's output requests (paper Sec. 3.1): E_x, E_y and B_z on
+    the plane through the laser axis (z = n_z / 2 in 3D, the whole grid in 2D),
+    the electron charge density on the same plane, and the electrons' phase
+    space in the foil's x range (every 32nd particle), each every `every` steps."""
+    n = w.n
+    plane = ({"lo": [0, 0, n[2] // 2], "hi": [n[0], n[1], n[2] // 2 + 1]} if w.dims == 3
+             else {"lo": [0, 0], "hi": [n[0], n[1]]})
+    foil = {"lo": [max(w.foil_x[0] - 8, 0)] + [0] * (w.dims - 1),
+            "hi": [min(w.foil_x[1] + 40, n[0])] + list(n[1:w.dims])}
+    return [{"name": "fields", "kind": "fields", "components": ["Ex", "Ey", "Bz"], "box": plane, "every": every},
+            {"name": "rho_e", "kind": "density", "species": [0], "box": plane, "every": every},
+            {"name": "electrons", "kind": "particles", "species": 0, "cells": foil, "subsample": 32, "every": every}]
+
+
+def output_overhead(sim, w, steps: int, every: int) -> dict:
+    """Time per step over `steps` steps, one pic_step call per step, without
+    and then with the output manager writing laser_outputs(w, every) to a
+    scratch directory (device extraction on the step's stream, copies on a
+    side stream, writes on host threads)."""
+    import shutil
+    import tempfile
+
+    import torch
+
+    from paper_1503_02464_amd.outputs import OutputManager
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step(1)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    out = tempfile.mkdtemp(prefix="pic_outputs_")
+    try:
+        m = OutputManager(sim, laser_outputs(w, every), out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step(1)
+            m.after_step()
+        torch.cuda.synchronize()
+        stepped = time.perf_counter() - t0
+        m.flush()
+        drained = time.perf_counter() - t0
+        ext_ms, ext_n = m.extraction_ms()
+        m.close()
+        nbytes = sum(os.path.getsize(os.path.join(d, f)) for d, _, fs in os.walk(out) for f in fs)
+        files = m.files
+    finally:
+        shutil.rmtree(out, ignore_errors=True)
+    return {"every": every, "steps": steps, "files": files, "bytes_written": nbytes,
+            "ms_per_step_without": plain / steps * 1e3, "ms_per_step_with": stepped / steps * 1e3,
+            "overhead": stepped / plain - 1.0, "ms_until_written": drained * 1e3,
+            "extraction_ms_per_output": ext_ms / max(ext_n, 1), "outputs": ext_n,
+            "written_GBs": nbytes / drained / 1e9,
+            "requests": [r["name"] for r in laser_outputs(w, every)]}
+
+
 def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     """A laser-on-foil box (open x faces, laser sheet, electrons + ions) in its
     launch configuration, FP32, timed over `steps` steps that start once the
@@ -317,6 +377,9 @@ def laser_foil_timing(w, steps: int, warmup: int) -> dict:
     tim = sim.get_timing()
     sim.set_timing(False)
     diag = sim.diagnostics()
+    outs = output_overhead(sim, w, steps, every=4)
+    log(f"{w.name}: outputs every 4 steps: {outs['ms_per_step_without']:.3f} -> {outs['ms_per_step_with']:.3f} ms "
+        f"per step ({outs['files']} files, {outs['bytes_written'] / 2**20:.1f} MiB)")
     sim.close()
     return {"workload": w.name, "particles": npart, "cells": w.ncells, "steps": steps,
             "timed_from_step": reach, "pulse_peak_at_foil_step": reach,
@@ -325,7 +388,7 @@ def laser_foil_timing(w, steps: int, warmup: int) -> dict:
             "stragglers_last_launch": strays,
             "ms_per_step": el / steps * 1e3, "pushes_per_s": 0.5 * (live0 + live1) * steps / el,
             "phases_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in tim.items()},
-            "energy": {k: diag[k] for k in ("UE", "UB", "K")}}
+            "energy": {k: diag[k] for k in ("UE", "UB", "K")}, "outputs": outs}
 
 
 def two_stream_timing(steps: int, warmup: int, scale: int = 1) -> dict:

@@ -300,6 +300,56 @@ pic_status pic_charge_density(pic_ctx *ctx, const pic_species *sp, int32_t nspec
 pic_status pic_diagnostics_noalloc(pic_ctx *ctx, const pic_species *sp, int32_t nspecies, const pic_fields *f,
                                    double *out_host, void *stream);
 
+/* ---- Outputs (Sec. 3.1: reduced-dimension outputs, such as a plane of a 3D
+ * box or a line of a 2D one, and subdomain outputs, such as a small box inside
+ * a large one; when and how often to write them is the caller's schedule).
+ *
+ * A box of grid points (or of cells, for particles): along each dimension d
+ * the indices lo[d], lo[d] + stride[d], ... below hi[d], with
+ * 0 <= lo[d] <= hi[d] <= n[d] and stride[d] >= 1 (in 2D lo[2] = 0, hi[2] = 1).
+ * A plane is a box one index thick along one axis, a line one index thick
+ * along two; lo[d] == hi[d] selects nothing. */
+typedef struct {
+    int32_t lo[3];
+    int32_t hi[3];
+    int32_t stride[3];
+} pic_box;
+
+#define PIC_MAX_EXTRACT_GRIDS 16
+
+/* Copy the values of ngrids grids at the points of box into dst, densely
+ * packed and bit for bit.  Each grid is a device array laid out as the fields
+ * (n[0]*n[1]*n[2] elements, x fastest) of elem_bytes = 4 or 8 bytes: E, B or
+ * J components of the state's precision, or FP64 grids such as the charge
+ * density of pic_charge_density.  With m_d = ceil((hi[d] - lo[d]) / stride[d])
+ * points per axis, grid g's value at the point (a, b, c) of the box (the
+ * a-th selected x index, and so on) lands at
+ *   dst[((g * m_2 + c) * m_1 + b) * m_0 + a],
+ * so dst (device, caller-owned) must hold ngrids * m_0 * m_1 * m_2 elements.
+ * Each value keeps its grid's position (the Yee positions above for the field
+ * components).  Needs no workspace; enqueues on the stream without
+ * synchronising.  PIC_EINVAL for a bad box, elem_bytes, grid count or null
+ * pointer. */
+pic_status pic_extract_grid(pic_ctx *ctx, const void *const *grids, int32_t ngrids, int32_t elem_bytes,
+                            const pic_box *box, void *dst, void *stream);
+
+/* Phase-space records of one species (Sec. 3.1: the particles' phase space
+ * output; Sec. 3.3: seven values per particle): the particles whose cell
+ * lies in the box of cells (its lo and hi; stride is ignored) and whose
+ * storage index is a multiple of every (>= 1, a subsampling of the storage
+ * order), with open x faces excluding removed (weight-0) ones.  Each selected
+ * particle, in storage order, writes one record of dims + 4 values of the
+ * state's precision into dst (device, caller-owned, capacity records):
+ *   x_0 .. x_{dims-1}, u_0, u_1, u_2, w,
+ * with x_d = (cell_d + off_d) dx_d evaluated in double and rounded once to
+ * the state's precision.  *count (a device int64) receives the number
+ * selected, also when it exceeds capacity: then only the first capacity
+ * records are written.  Uses the workspace (per-chunk counts); enqueues on
+ * the stream without synchronising.  PIC_EINVAL for a bad box, every < 1,
+ * capacity < 0, a null count, or a null dst with capacity > 0. */
+pic_status pic_extract_particles(pic_ctx *ctx, const pic_species *sp, const pic_box *cells, int64_t every,
+                                 void *dst, int64_t capacity, int64_t *count, void *stream);
+
 /* ---- Reverse mode (adjoint) of one step, for gradients of a loss of the
  * final fields through K steps (the discrete adjoint of steps 1-4 above).
  *

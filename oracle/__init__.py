@@ -458,3 +458,43 @@ def tile_sort(grid: Grid, tile: tuple, sp: dict) -> tuple:
     start = np.zeros(ntiles + 1, np.int64)
     start[1:] = np.cumsum(counts)
     return out, start
+
+
+# ---- Outputs (paper Sec. 3.1: reduced-dimension outputs, e.g. a plane of a
+# 3D box or a line of a 2D one, and subdomain outputs, e.g. a small box in a
+# large one).  Plain definitions by indexing, for the output extraction.
+
+def box_axes(lo, hi, stride) -> list:
+    """Selected indices per dimension: lo[d], lo[d] + stride[d], ... below hi[d]."""
+    return [np.arange(lo[d], hi[d], stride[d], dtype=np.int64) for d in range(3)]
+
+
+def extract_box(grid: Grid, grids: list, lo, hi, stride) -> np.ndarray:
+    """Values of each flat grid (x fastest) at the points of the box, as an
+    array of shape (len(grids), m_z, m_y, m_x): entry [g, c, b, a] is grid g
+    at the a-th selected x index, b-th y index and c-th z index."""
+    ix, iy, iz = box_axes(lo, hi, stride)
+    n0, n1 = grid.n[0], grid.n[1]
+    out = np.empty((len(grids), iz.size, iy.size, ix.size), dtype=np.asarray(grids[0]).dtype)
+    for g, F in enumerate(grids):
+        for c, k in enumerate(iz):
+            for b, j in enumerate(iy):
+                out[g, c, b, :] = np.asarray(F)[ix + n0 * (j + n1 * k)]
+    return out
+
+
+def phase_space(grid: Grid, sp: dict, lo, hi, every: int = 1, skip_weightless: bool = False) -> np.ndarray:
+    """Phase-space records (Sec. 3.3: positions, momenta, weight) of the
+    particles, in storage order, whose storage index is a multiple of every and
+    whose cell lies in [lo, hi) along each dimension (and, with
+    skip_weightless, whose weight is not 0): rows x_0 .. x_{dims-1}, u_0, u_1,
+    u_2, w with x_d = (cell_d + off_d) dx_d in FP64."""
+    dims = grid.dims
+    rows = []
+    for i in range(0, sp["w"].shape[0], every):
+        inside = all(lo[d] <= sp["cell"][d, i] < hi[d] for d in range(dims))
+        if not inside or (skip_weightless and sp["w"][i] == 0.0):
+            continue
+        x = [(float(sp["cell"][d, i]) + float(sp["off"][d, i])) * grid.dx[d] for d in range(dims)]
+        rows.append(x + [float(sp["u"][0, i]), float(sp["u"][1, i]), float(sp["u"][2, i]), float(sp["w"][i])])
+    return np.array(rows, dtype=np.float64).reshape(len(rows), dims + 4)

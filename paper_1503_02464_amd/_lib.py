@@ -17,6 +17,7 @@ PIC_ACC_AUTO, PIC_ACC_FP32, PIC_ACC_FP64, PIC_ACC_FIX64 = 0, 1, 2, 3
 PIC_NDIAG = 8
 PIC_NOALLOC_MAX_CELLS = 1 << 22
 PIC_NPHASE = 4
+PIC_MAX_EXTRACT_GRIDS = 16
 PHASES = ("sort", "zero_current", "push_deposit", "yee")
 
 _c3i = ctypes.c_int32 * 3
@@ -79,6 +80,10 @@ class Species(ctypes.Structure):
     ]
 
 
+class Box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3), ("stride", ctypes.c_int32 * 3)]
+
+
 class SpeciesAdjoint(ctypes.Structure):
     _fields_ = [("x", _c3p), ("u", _c3p)]
 
@@ -125,6 +130,10 @@ def load(path: str = LIB_PATH):
                                     ctypes.c_void_p]),
         "pic_diagnostics_noalloc": (st, [ctx, P(Species), ctypes.c_int32, P(Fields), P(ctypes.c_double),
                                          ctypes.c_void_p]),
+        "pic_extract_grid": (st, [ctx, P(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32, P(Box), ctypes.c_void_p,
+                                  ctypes.c_void_p]),
+        "pic_extract_particles": (st, [ctx, P(Species), P(Box), ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
         "pic_check": (st, [ctx, ctypes.c_void_p]),
         "pic_set_timing": (st, [ctx, ctypes.c_int32]),
         "pic_get_timing": (st, [ctx, P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]),

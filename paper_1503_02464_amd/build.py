@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libpic.so")
-SOURCES = ["api.cpp", "particles.hip", "fields.hip", "sort.hip", "diag.hip", "adjoint.hip"]
+SOURCES = ["api.cpp", "particles.hip", "fields.hip", "sort.hip", "diag.hip", "adjoint.hip", "output.hip"]
 ARCH = "gfx950"
 
 

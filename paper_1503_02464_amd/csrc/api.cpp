@@ -274,6 +274,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.rho_prev = take(static_cast<size_t>(ncells) * 8);
   w.gauss_prev = take(static_cast<size_t>(ncells) * 8);
   w.mur_old = take(p->open_x ? static_cast<size_t>(8) * p->n[1] * p->n[2] * c->elem : 0);
+  w.select_base = take(static_cast<size_t>((p->max_particles + pic::kSelectChunk - 1) / pic::kSelectChunk + 1) * 8);
   w.total = off;
   *out = c;
   return PIC_OK;
@@ -522,6 +523,47 @@ pic_status pic_diagnostics_noalloc(pic_ctx *c, const pic_species *sp, int32_t ns
   for (int i = 0; i < PIC_NDIAG; ++i) out[i] = res[i];
   for (int i = 0; i < 4; ++i)
     if (!std::isfinite(res[i])) return fail(c, PIC_ENAN, "non-finite energy or charge");
+  return PIC_OK;
+}
+
+namespace {
+// A box inside the grid (points or cells): 0 <= lo <= hi <= n, and stride >= 1
+// where the stride is used.
+bool box_ok(const pic_ctx *c, const pic_box *b, bool strided) {
+  if (!b) return false;
+  for (int d = 0; d < 3; ++d)
+    if (b->lo[d] < 0 || b->hi[d] < b->lo[d] || b->hi[d] > c->n[d] || (strided && b->stride[d] < 1)) return false;
+  return true;
+}
+}  // namespace
+
+pic_status pic_extract_grid(pic_ctx *c, const void *const *grids, int32_t ngrids, int32_t elem_bytes,
+                            const pic_box *box, void *dst, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (!box_ok(c, box, true)) return fail(c, PIC_EINVAL, "bad box: need 0 <= lo <= hi <= n and stride >= 1");
+  if (ngrids < 1 || ngrids > pic::kMaxExtractGrids || !grids)
+    return fail(c, PIC_EINVAL, "between 1 and PIC_MAX_EXTRACT_GRIDS grids");
+  if (elem_bytes != 4 && elem_bytes != 8) return fail(c, PIC_EINVAL, "elem_bytes must be 4 or 8");
+  for (int g = 0; g < ngrids; ++g)
+    if (!grids[g]) return fail(c, PIC_EINVAL, "null grid");
+  const int64_t pts = pic::box_points(*box, 0) * pic::box_points(*box, 1) * pic::box_points(*box, 2);
+  if (pts > 0 && !dst) return fail(c, PIC_EINVAL, "null dst");
+  hipError_t e = pic::launch_extract_grid(*c, grids, ngrids, elem_bytes, *box, dst, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "extract_grid");
+  return PIC_OK;
+}
+
+pic_status pic_extract_particles(pic_ctx *c, const pic_species *sp, const pic_box *cells, int64_t every, void *dst,
+                                 int64_t capacity, int64_t *count, void *stream) {
+  if (!c) return PIC_EINVAL;
+  if (pic_status s = check_ws(c)) return s;
+  if (!box_ok(c, cells, false)) return fail(c, PIC_EINVAL, "bad cell box: need 0 <= lo <= hi <= n");
+  if (every < 1 || capacity < 0 || !count || (capacity > 0 && !dst))
+    return fail(c, PIC_EINVAL, "bad particle output arguments");
+  if (!species_ok(c, sp, false)) return fail(c, PIC_EINVAL, "bad species");
+  hipError_t e = pic::launch_extract_particles(*c, *sp, *cells, every, dst, capacity, count,
+                                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "extract_particles");
   return PIC_OK;
 }
 

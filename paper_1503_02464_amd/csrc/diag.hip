@@ -121,13 +121,22 @@ __global__ void __launch_bounds__(kB) k_rho(const int32_t *cell, const T *o0, co
 // The same on sorted particles, one workgroup per tile: the tile's charge is
 // accumulated in an LDS box (double) and added to HBM once.  Particles whose
 // cell lies more than `slack` cells outside their tile add to HBM directly.
+// With `live` (the non-empty tiles of the species' last sort, their count at
+// [ntiles]) workgroup b takes the b-th non-empty tile, so that the busy tiles
+// of a sparse box (a foil) are dealt over every XCD rather than the few that
+// tile-index order maps them to.
 template <typename T, int D, int M>
 __global__ void __launch_bounds__(256) k_rho_tiled(const int32_t *cell, const T *o0, const T *o1, const T *o2,
-                                                   const T *w, const int32_t *tile_start, int64_t np, double qdv,
+                                                   const T *w, const int32_t *tile_start, const int32_t *live,
+                                                   int64_t ntiles, int64_t np, double qdv,
                                                    int b0, int b1, int m0, int m1, int m2, int n0, int n1, int n2,
                                                    int L0, int L1, int L2, int nt0, int nt1, int slack, double *rho) {
   extern __shared__ double box[];
-  const int64_t tile = blockIdx.x;
+  int64_t tile = blockIdx.x;
+  if (live) {
+    if (tile >= live[ntiles]) return;
+    tile = live[tile];
+  }
   int64_t pbeg = tile_start[tile], pend = tile_start[tile + 1];
   pbeg = pbeg < 0 ? 0 : (pbeg > np ? np : pbeg);
   pend = pend > np ? np : pend;
@@ -304,7 +313,8 @@ hipError_t charge_grid(const pic_ctx &c, const pic_species *sp, int nsp, double 
       if (box <= 64 * 1024) {
         hipLaunchKernelGGL((k_rho_tiled<T, D, M>), dim3(static_cast<unsigned>(c.ntiles)), dim3(kB), box, s, q.cell,
                            static_cast<const T *>(q.off[0]), static_cast<const T *>(q.off[1]),
-                           static_cast<const T *>(q.off[2]), static_cast<const T *>(q.w), q.tile_start, q.np,
+                           static_cast<const T *>(q.off[2]), static_cast<const T *>(q.w), q.tile_start,
+                           live_tiles(c, q), c.ntiles, q.np,
                            q.q / dV, c.bits[0], c.bits[1], (1 << c.bits[0]) - 1, (1 << c.bits[1]) - 1, (1 << c.bits[2]) - 1,
                            static_cast<int>(c.n[0]), static_cast<int>(c.n[1]), static_cast<int>(c.n[2]),
                            c.p.tile[0], c.p.tile[1], c.p.tile[2], c.ntile[0], c.ntile[1], sl, rho);

@@ -22,6 +22,10 @@ constexpr int kDiagSlots = PIC_NDIAG;  // UE UB K Q max|rho| max|G| max|dG| max|
 // lives in a fixed device array, and the devices it keeps an address for.
 constexpr int64_t kScratchCells = PIC_NOALLOC_MAX_CELLS;
 constexpr int kMaxDevices = 64;
+// Output extraction: grids per call, and the storage slots one workgroup of
+// the particle selection scans (its count is one workspace entry).
+constexpr int kMaxExtractGrids = PIC_MAX_EXTRACT_GRIDS;
+constexpr int64_t kSelectChunk = 8192;
 // Largest capacity of the fused kernel's list of particles that need the
 // wide Esirkepov window (their nearest node changed), per precision; the
 // context lowers it to what the LDS left by the field and current boxes holds.
@@ -62,6 +66,7 @@ struct Workspace {
   size_t rho_prev = 0;    // double[ncells]
   size_t gauss_prev = 0;  // double[ncells]
   size_t mur_old = 0;     // T[8][n1 * n2]: E_y, E_z^n of the planes next to the open x faces
+  size_t select_base = 0; // int64[ceil(max_particles / kSelectChunk) + 1]: particle selection per chunk
   size_t total = 0;
 };
 
@@ -184,5 +189,15 @@ hipError_t scratch_address(double **out);
 hipError_t launch_diagnostics_noalloc(const pic_ctx &c, const pic_species *sp, int nspecies, const pic_fields &f,
                                       double *scratch, hipStream_t s);
 size_t scratch_result_offset();
+
+// Points of a box along dimension d (0 when hi <= lo).
+inline int64_t box_points(const pic_box &b, int d) {
+  return b.hi[d] > b.lo[d] ? (static_cast<int64_t>(b.hi[d]) - b.lo[d] + b.stride[d] - 1) / b.stride[d] : 0;
+}
+// Output extraction (callers validate the box against the grid).
+hipError_t launch_extract_grid(const pic_ctx &c, const void *const *grids, int32_t ngrids, int32_t elem_bytes,
+                               const pic_box &box, void *dst, hipStream_t s);
+hipError_t launch_extract_particles(const pic_ctx &c, const pic_species &sp, const pic_box &cells, int64_t every,
+                                    void *dst, int64_t capacity, int64_t *count, hipStream_t s);
 
 }  // namespace pic

@@ -352,6 +352,61 @@ class Simulation:
         torch.cuda.synchronize()
         return (rho.cpu().numpy(), g.cpu().numpy()) if gauss else rho.cpu().numpy()
 
+    # -- outputs: device-side extraction (pic_extract_grid / _particles) ----
+    def box(self, lo=None, hi=None, stride=None) -> L.Box:
+        """A pic_box over this grid (defaults: the whole grid, stride 1)."""
+        lo = tuple(int(v) for v in lo) + (0, 0, 0)[len(lo):] if lo is not None else (0, 0, 0)
+        hi = tuple(int(v) for v in hi) + (1, 1, 1)[len(hi):] if hi is not None else self.n
+        stride = tuple(int(v) for v in stride) + (1, 1, 1)[len(stride):] if stride is not None else (1, 1, 1)
+        if self.dims == 2:
+            lo, hi = (lo[0], lo[1], 0), (hi[0], hi[1], 1)
+        return L.Box(lo=L._c3i(*lo), hi=L._c3i(*hi), stride=L._c3i(*stride))
+
+    @staticmethod
+    def box_shape(b: L.Box) -> tuple:
+        """Points per axis of a box, (m_x, m_y, m_z)."""
+        return tuple(max(0, -(-(b.hi[d] - b.lo[d]) // b.stride[d])) for d in range(3))
+
+    def extract_grid(self, grids: list, b: L.Box, out: torch.Tensor | None = None) -> torch.Tensor:
+        """The values of device grids (tensors of ncells elements, one dtype)
+        at the box's points, packed as (len(grids), m_z, m_y, m_x) into a device
+        tensor; enqueued on the current stream, not synchronised."""
+        mx, my, mz = self.box_shape(b)
+        shape = (len(grids), mz, my, mx)
+        dtype = grids[0].dtype
+        if out is None:
+            out = torch.empty(shape, dtype=dtype, device=self.device)
+        arr = (ctypes.c_void_p * len(grids))(*[_ptr(g) for g in grids])
+        self._call(self.lib.pic_extract_grid(self.ctx, arr, len(grids), grids[0].element_size(), ctypes.byref(b),
+                                             ctypes.c_void_p(_ptr(out)), ctypes.c_void_p(_stream())),
+                   "pic_extract_grid")
+        return out
+
+    def extract_particles(self, s: SpeciesState, cells: L.Box, every: int, out: torch.Tensor,
+                          count: torch.Tensor) -> None:
+        """Phase-space records (dims + 4 values each) of the species' particles
+        in the cell box, every every-th in storage order, into out (a device
+        tensor of capacity x (dims + 4) values of the state's dtype); the
+        number selected goes to count (a device int64 tensor of one element).
+        Enqueued on the current stream, not synchronised."""
+        rec = self.dims + 4
+        assert out.dtype == self.dtype and out.numel() % rec == 0 and count.dtype == torch.int64
+        self._call(self.lib.pic_extract_particles(self.ctx, ctypes.byref(s.struct), ctypes.byref(cells), int(every),
+                                                  ctypes.c_void_p(_ptr(out)), out.numel() // rec,
+                                                  ctypes.c_void_p(_ptr(count)), ctypes.c_void_p(_stream())),
+                   "pic_extract_particles")
+
+    def charge_density_into(self, rho: torch.Tensor, species: list | None = None) -> None:
+        """The FP64 charge density of the given species into the device grid
+        rho (pic_charge_density), enqueued on the current stream."""
+        sp = species if species is not None else self.species
+        arr = (L.Species * max(len(sp), 1))()
+        for i, s in enumerate(sp):
+            arr[i] = s.struct
+        self._call(self.lib.pic_charge_density(self.ctx, arr, len(sp), ctypes.byref(self.fstruct),
+                                               ctypes.c_void_p(_ptr(rho)), ctypes.c_void_p(None),
+                                               ctypes.c_void_p(_stream())), "pic_charge_density")
+
     def check(self) -> None:
         self._call(self.lib.pic_check(self.ctx, ctypes.c_void_p(_stream())), "pic_check")
 

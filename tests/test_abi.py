@@ -116,11 +116,13 @@ def test_header_and_binding_agree():
                  "PIC_ECROSS = -5", "PIC_ENAN = -6", "PIC_ESTATE = -7"):
         assert name in text
     assert "#define PIC_NDIAG 8" in text and "#define PIC_NPHASE 4" in text
+    assert f"#define PIC_MAX_EXTRACT_GRIDS {L.PIC_MAX_EXTRACT_GRIDS}" in text
 
 
 def test_struct_layout_matches_header(tmp_path):
     """Offsets of every field of the ABI structs, from gcc on pic.h, equal the ctypes mirror."""
-    structs = {"pic_params": L.Params, "pic_fields": L.Fields, "pic_species": L.Species, "pic_laser": L.Laser}
+    structs = {"pic_params": L.Params, "pic_fields": L.Fields, "pic_species": L.Species, "pic_laser": L.Laser,
+               "pic_box": L.Box}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pic.h"', "int main(void){"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
@@ -181,4 +183,47 @@ def test_adjoint_refuses_open_faces(lib):
     f = L.Fields()
     assert lib.pic_yee_adjoint(ctx, ctypes.byref(f), None) == L.PIC_EINVAL
     assert lib.pic_energy_adjoint(ctx, ctypes.byref(f), ctypes.byref(f), 1.0, None) == L.PIC_EINVAL
+    lib.pic_destroy(ctx)
+
+
+def box(lo, hi, stride=(1, 1, 1)):
+    return L.Box(lo=(ctypes.c_int32 * 3)(*lo), hi=(ctypes.c_int32 * 3)(*hi), stride=(ctypes.c_int32 * 3)(*stride))
+
+
+BAD_BOXES = [((-1, 0, 0), (4, 4, 4), (1, 1, 1)), ((0, 0, 0), (17, 4, 4), (1, 1, 1)), ((5, 0, 0), (4, 4, 4), (1, 1, 1)),
+             ((0, 0, 0), (4, 4, 4), (0, 1, 1)), ((0, 0, 0), (4, 4, 16 + 1), (1, 1, 1))]
+
+
+@pytest.mark.parametrize("lo,hi,stride", BAD_BOXES)
+def test_extract_grid_refuses_bad_boxes(lib, lo, hi, stride):
+    st, ctx = init(lib, params())
+    grids = (ctypes.c_void_p * 1)(0x1000)
+    b = box(lo, hi, stride)
+    assert lib.pic_extract_grid(ctx, grids, 1, 4, ctypes.byref(b), ctypes.c_void_p(0x2000), None) == L.PIC_EINVAL
+    assert b"box" in lib.pic_last_error(ctx)
+    lib.pic_destroy(ctx)
+
+
+def test_extract_grid_argument_checks(lib):
+    st, ctx = init(lib, params())
+    b = box((0, 0, 0), (16, 16, 1))
+    grids = (ctypes.c_void_p * 17)(*([0x1000] * 17))
+    dst = ctypes.c_void_p(0x2000)
+    assert lib.pic_extract_grid(ctx, grids, 0, 4, ctypes.byref(b), dst, None) == L.PIC_EINVAL
+    assert lib.pic_extract_grid(ctx, grids, 17, 4, ctypes.byref(b), dst, None) == L.PIC_EINVAL
+    assert lib.pic_extract_grid(ctx, grids, 1, 2, ctypes.byref(b), dst, None) == L.PIC_EINVAL
+    assert lib.pic_extract_grid(ctx, grids, 1, 4, None, dst, None) == L.PIC_EINVAL
+    assert lib.pic_extract_grid(ctx, grids, 1, 4, ctypes.byref(b), None, None) == L.PIC_EINVAL
+    nul = (ctypes.c_void_p * 2)(0x1000, None)
+    assert lib.pic_extract_grid(ctx, nul, 2, 4, ctypes.byref(b), dst, None) == L.PIC_EINVAL
+    lib.pic_destroy(ctx)
+
+
+def test_extract_particles_argument_checks(lib):
+    st, ctx = init(lib, params())
+    sp = L.Species()
+    cells = box((0, 0, 0), (16, 16, 16), (0, 0, 0))  # the stride of a cell box is not used
+    cnt = ctypes.c_void_p(0x3000)
+    # no workspace yet
+    assert lib.pic_extract_particles(ctx, ctypes.byref(sp), ctypes.byref(cells), 1, None, 0, cnt, None) == L.PIC_ENOMEM
     lib.pic_destroy(ctx)

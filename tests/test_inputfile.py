@@ -28,7 +28,22 @@ def doc(name):
 
 
 def test_every_run_file_is_covered():
-    assert sorted(os.listdir(RUNS)) == sorted(CASES)
+    runs = [f for f in os.listdir(RUNS) if not f.endswith("_outputs.json")]
+    assert sorted(runs) == sorted(CASES)
+
+
+def test_output_requests_file_fits_its_run():
+    """The example output requests (Sec. 3.1) of the 3D laser-foil run parse
+    against that run's grid and species."""
+    from paper_1503_02464_amd.outputs import parse_requests
+    spec = inputfile.load(os.path.join(RUNS, "laser_foil_3d.json"))
+    w = spec.workload()
+    with open(os.path.join(RUNS, "laser_foil_3d_outputs.json")) as f:
+        reqs = parse_requests(json.load(f), w.dims, w.n, 2)
+    kinds = sorted({r.kind for r in reqs})
+    assert kinds == ["density", "fields", "particles"]
+    line = [r for r in reqs if r.name == "ey_axis_line"][0]
+    assert line.points() == (512, 1, 1) and line.fires(400) and not line.fires(401) and not line.fires(502)
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
