@@ -83,11 +83,11 @@ enum { PIC_FP32 = 0, PIC_FP64 = 1 };
  *   FIX64 (FP32 state only): 64-bit fixed point.  Each contribution, bounded
  *     by |q/dV (dx_d/dt)| w_max (|q|/dA w_max for J_z in 2D) with w_max the
  *     largest |w| among the tile's particles, is scaled by a power of two so
- *     that the bound is at most 2^30, rounded to an integer and added with a
+ *     that the bound is at most 2^30, truncated to an integer and added with a
  *     64-bit integer LDS atomic; the merge scales the tile's sums back.  The
- *     rounding is at most 2^-31 of the bound per contribution, below the FP32
- *     arithmetic's own.  Integer LDS atomics cost about half as much as double
- *     ones on gfx950 when lanes collide on banks.
+ *     truncation is below 2^-30 of the bound per contribution, below the FP32
+ *     rounding of the largest contributions.  Integer LDS atomics cost about
+ *     half as much as double ones on gfx950 when lanes collide on banks.
  *   FP32: single-precision LDS atomics (accepted for an FP32 state; slow on
  *     gfx950, where the LDS unit serialises them lane by lane).
  *   AUTO (the default): FIX64 for an FP32 state, FP64 for an FP64 state. */

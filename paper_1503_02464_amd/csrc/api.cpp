@@ -226,8 +226,15 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
     }
   }
   c->jxy = pic::current_plane_stride(c->rj[0], c->rj[1], p->dims);
-  const size_t boxes = 6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] * c->elem +
-                       3 * static_cast<size_t>(c->jxy) * c->rj[2] * jelem;
+  const size_t jbox = 3 * static_cast<size_t>(c->jxy) * c->rj[2] * jelem;
+  // The field box's rows are padded to an even length where it fits: the
+  // gather then reads every run of three values as an aligned pair and a
+  // single (the fixed-shape kernels assume it for their tile shapes).
+  if ((c->rf[0] & 1) &&
+      6 * static_cast<size_t>(c->rf[0] + 1) * c->rf[1] * c->rf[2] * c->elem + jbox + pic::cross_list_bytes(c->elem, 0) <=
+          pic::kLdsLimit)
+    c->rf[0] += 1;
+  const size_t boxes = 6 * static_cast<size_t>(c->rf[0]) * c->rf[1] * c->rf[2] * c->elem + jbox;
   if (boxes + pic::cross_list_bytes(c->elem, 0) > pic::kLdsLimit) {
     delete c;
     return PIC_EINVAL;

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace pic {
 
@@ -62,12 +63,55 @@ __device__ __forceinline__ void half_weights(int c, T o, T w[M + 1], int &base) 
   }
 }
 
+// Accessors whose x runs can be read as aligned pairs (see interp).
+template <class A, class = void>
+struct HasPairs : std::false_type {};
+template <class A>
+struct HasPairs<A, std::void_t<decltype(A::kPairs)>> : std::bool_constant<A::kPairs> {};
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+
 // Sum over the (M+1)^D points of one component with per-axis weights.
 template <typename T, int D, int M, class Acc>
 __device__ __forceinline__ T interp(const Acc &acc, int comp, const T *wx, int bx, const T *wy, int by, const T *wz,
                                     int bz) {
   T s = T(0);
-  if constexpr (D == 3) {
+  if constexpr (M == 2 && HasPairs<Acc>::value) {
+    // Every row of the box starts at an even element, so each run of three
+    // values is one aligned pair and one single: (v0 v1 | v2) when the run
+    // starts at an even element, (v0 | v1 v2) when odd.  The weights are
+    // rotated once to match, and every row takes one read of two values and
+    // one of one value, where three single reads cost the LDS about twice as
+    // much (its cost follows the number of addresses more than the bytes).
+    static_assert(sizeof(typename Acc::value_type) == sizeof(T), "pair reads need the state's type");
+    using P2 = typename Pair<T>::type;
+    const int e0 = acc.index(comp, bx, by, D == 3 ? bz : 0);
+    const bool odd = (e0 & 1) != 0;
+    const T a = odd ? wx[1] : wx[0], b = odd ? wx[2] : wx[1], c = odd ? wx[0] : wx[2];
+    const P2 *pr = reinterpret_cast<const P2 *>(acc.base) + ((e0 + 1) >> 1);
+    const T *sg = acc.base + (odd ? e0 : e0 + 2);
+#pragma unroll
+    for (int k = 0; k <= (D == 3 ? M : 0); ++k) {
+      T sy = T(0);
+#pragma unroll
+      for (int j = 0; j <= M; ++j) {
+        const int off = Acc::kSX * j + Acc::kSXY * k;
+        const P2 p = pr[off >> 1];
+        sy += wy[j] * (a * p.x + b * p.y + c * sg[off]);
+      }
+      if constexpr (D == 3) s += wz[k] * sy;
+      else s = sy;
+    }
+  } else if constexpr (D == 3) {
 #pragma unroll
     for (int k = 0; k <= M; ++k) {
       T sy = T(0);
@@ -383,16 +427,17 @@ __device__ __forceinline__ void deposit(const Acc &acc, const int c0[3], const T
 
 // One addition into an on-chip current accumulator of type S.  Floating
 // accumulators add the value; the 64-bit fixed-point one (unsigned long long,
-// two's complement) adds v rounded to the nearest integer: its callers pass
-// contributions already scaled by 2^shift (the coefficients of the current
-// carry the factor), which keeps every one within 2^30.
+// two's complement) adds v truncated to an integer (toward zero: one
+// conversion, no rounding step): its callers pass contributions already
+// scaled by 2^shift (the coefficients of the current carry the factor), which
+// keeps every one within 2^30, so the truncation is below 2^-30 of the bound.
 template <typename S, typename V>
 __device__ __forceinline__ void lds_add(S *p, V v) {
   atomicAdd(p, static_cast<S>(v));
 }
 template <typename V>
 __device__ __forceinline__ void lds_add(unsigned long long *p, V v) {
-  const int k = static_cast<int>(rintf(static_cast<float>(v)));
+  const int k = static_cast<int>(static_cast<float>(v));
   atomicAdd(p, static_cast<unsigned long long>(static_cast<long long>(k)));
 }
 
@@ -448,7 +493,14 @@ struct LdsFields {
 // the stored type; values added are converted to it.
 template <typename S, int SX, int SXY, int VOL, int OX, int OY, int OZ>
 struct LdsBox {
+  using value_type = S;
   S *base;
+  static constexpr int kSX = SX, kSXY = SXY;
+  // floating values with even strides: x runs read as aligned pairs (interp)
+  static constexpr bool kPairs = std::is_floating_point<S>::value && SX % 2 == 0 && SXY % 2 == 0 && VOL % 2 == 0;
+  __device__ __forceinline__ int index(int comp, int i, int j, int k) const {
+    return comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ);
+  }
   __device__ __forceinline__ S load(int comp, int i, int j, int k) const {
     return base[comp * VOL + (i + OX) + SX * (j + OY) + SXY * (k + OZ)];
   }

@@ -378,7 +378,9 @@ template <int D, int M, int LX, int LY, int LZ, int SL>
 struct FixedGeom {
   static constexpr int L0 = LX, L1 = LY, L2 = D == 3 ? LZ : 1, S = SL;
   static constexpr int FLO = 1 + SL, JLO = M + SL;
-  static constexpr int FX = LX + 1 + M + 2 * SL, FY = LY + 1 + M + 2 * SL, FZ = D == 3 ? LZ + 1 + M + 2 * SL : 1;
+  // the field box's rows are padded to an even length (pair reads in the gather)
+  static constexpr int FX = (LX + 1 + M + 2 * SL + 1) / 2 * 2, FY = LY + 1 + M + 2 * SL,
+                       FZ = D == 3 ? LZ + 1 + M + 2 * SL : 1;
   static constexpr int JX = LX + 2 * M + 1 + 2 * SL, JY = LY + 2 * M + 1 + 2 * SL,
                        JZ = D == 3 ? LZ + 2 * M + 1 + 2 * SL : 1;
   static constexpr int JXY = current_plane_stride(JX, JY, D);
@@ -669,18 +671,15 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           }
           key = idx & 15;
         }
-        int before = 0, run = 0;
-        uint64_t mine = 0;
+        int k = 0, run = 0;
 #pragma unroll
         for (int r = 0; r <= 16; ++r) {
           const uint64_t m = __ballot(key == r);
-          if (key == r) {
-            mine = m;
-            before = run;
-          }
+          const int t = static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+              static_cast<uint32_t>(m >> 32), __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), static_cast<uint32_t>(run))));
+          k = key == r ? t : k;
           run += __popcll(m);
         }
-        const int k = before + __popcll(mine & below);
         const int to = ((k & 3) * 16 + (k >> 2)) * 4;
         T so[3], sn[3];
 #pragma unroll
@@ -1030,16 +1029,16 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   const int sl = c.p.slack;
   constexpr int BIG = sizeof(T) == 4 ? 1024 : 512;  // threads per workgroup of the fixed-shape kernels
   if constexpr (D == 3) {
-    if (sizeof(T) == 4 && L[0] == 8 && L[1] == 8 && L[2] == 8 && sl == 1)
+    if (sizeof(T) == 4 && L[0] == 8 && L[1] == 8 && L[2] == 8 && sl == 1 && c.rf[0] == FixedGeom<D, M, 8, 8, 8, 1>::FX)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 8, 1>, BIG>(c, sa, f, t, st);
-    else if (L[0] == 8 && L[1] == 8 && L[2] == 4 && sl == 1)
+    else if (L[0] == 8 && L[1] == 8 && L[2] == 4 && sl == 1 && c.rf[0] == FixedGeom<D, M, 8, 8, 4, 1>::FX)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 4, 1>, BIG>(c, sa, f, t, st);
     else
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   } else {
-    if (L[0] == 16 && L[1] == 16 && sl == 1)
+    if (L[0] == 16 && L[1] == 16 && sl == 1 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 1>::FX)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sa, f, t, st);
-    else if (L[0] == 16 && L[1] == 16 && sl == 2)  // the rollout, which never re-sorts
+    else if (L[0] == 16 && L[1] == 16 && sl == 2 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 2>::FX)  // the rollout
       e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sa, f, t, st);
     else
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);

@@ -61,10 +61,19 @@ def test_valid_init_and_queries(lib):
     bits = (ctypes.c_int32 * 3)()
     lib.pic_cell_bits(ctx, bits)
     assert tuple(bits) == (4, 4, 4)
-    # LDS: fields (8+1+2+2)^3 * 6 in FP32 + current (8+2+3+2)^3 * 3 accumulated in FP64, its
-    # planes padded from 15 * 15 = 225 to 231 elements (the next value that is 7 mod 16)
-    # + a list of 512 wide-window particles (8 FP32 values + one int each) and its length
-    assert lib.pic_tile_lds_bytes(ctx) == 13 ** 3 * 6 * 4 + 231 * 15 * 3 * 8 + 512 * 36 + 16
+    # LDS: fields (8+1+2+2)^3 * 6 in FP32, rows padded from 13 to 14 (even, for pair reads) +
+    # current (8+2+3+2)^3 * 3 accumulated in 64 bits, its planes padded from 15 * 15 = 225 to
+    # 231 elements (the next value that is 7 mod 16) + a list of 512 wide-window particles
+    # (8 FP32 values + one int each) and its length
+    assert lib.pic_tile_lds_bytes(ctx) == 14 * 13 * 13 * 6 * 4 + 231 * 15 * 3 * 8 + 512 * 36 + 16
+    # FP64 8x8x4 tiles: fields 14 x 13 x 9 doubles, current planes 231 x 11, 256 list entries of
+    # 8 doubles + an int; FP32 4^3 tiles: rows 9 -> 10, current planes 11 * 11 = 121 -> 135
+    for prec, tile, want in ((L.PIC_FP64, (8, 8, 4), 14 * 13 * 9 * 6 * 8 + 231 * 11 * 3 * 8 + 256 * 68 + 16),
+                             (L.PIC_FP32, (4, 4, 4), 10 * 9 * 9 * 6 * 4 + 135 * 11 * 3 * 8 + 512 * 36 + 16)):
+        st2, c2 = init(lib, params(prec=prec, tile=tile))
+        assert st2 == L.PIC_OK
+        assert lib.pic_tile_lds_bytes(c2) == want, (prec, tile)
+        lib.pic_destroy(c2)
     assert lib.pic_step_count(ctx) == 0
     lib.pic_destroy(ctx)
 
