@@ -234,13 +234,28 @@ __device__ __forceinline__ void esirkepov_rotated_2d(S *jl, int jx, int jvol, in
           lds_add(&jl[2 * jvol + org + i * st[0] + j * st[1]], jzc * (e.A[0][i] * e.S0[1][j] + e.Bf[0][i] * e.DS[1][j]));
 }
 
-template <typename T, int D>
+// Element i of a particle array.  With SMALL (index times element size
+// below 2^32) the byte offset is formed in 32 bits, so the arrays of one
+// particle share a single offset register against their scalar bases instead
+// of a 64-bit address each.
+template <bool SMALL, typename P>
+__device__ __forceinline__ P &elem(P *base, int64_t i) {
+  if constexpr (SMALL) {
+    using B = std::conditional_t<std::is_const<P>::value, const char, char>;
+    return *reinterpret_cast<P *>(reinterpret_cast<B *>(base) +
+                                  static_cast<uint32_t>(i) * static_cast<uint32_t>(sizeof(P)));
+  } else {
+    return base[i];
+  }
+}
+
+template <typename T, int D, bool SMALL = false>
 __device__ __forceinline__ void load_particle(const SpeciesArgs<T> &s, int64_t p, T o[3], T u[3]) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) o[d] = d < D ? s.off[d][p] : T(0);
-  u[0] = s.u[0][p];
-  u[1] = s.u[1][p];
-  u[2] = s.u[2][p];
+  for (int d = 0; d < 3; ++d) o[d] = d < D ? elem<SMALL>(s.off[d], p) : T(0);
+  u[0] = elem<SMALL>(s.u[0], p);
+  u[1] = elem<SMALL>(s.u[1], p);
+  u[2] = elem<SMALL>(s.u[2], p);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +452,8 @@ struct CurrentBox<T, RuntimeGeom, DD> {
 // FOLD: the launch takes over a sort's copy (reads through s.src, writes the
 // *_o arrays); otherwise it updates the particles in place and never touches
 // those pointers, which keeps them out of the registers.
-template <typename T, int D, int M, class G, int BLOCK, typename TJ, bool FOLD>
+// SMALL: every particle index of the launch (and of src) is below 2^30.
+template <typename T, int D, int M, class G, int BLOCK, typename TJ, bool FOLD, bool SMALL>
 __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                               GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -541,10 +557,10 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       for (int64_t q = pbeg + threadIdx.x; q < pend; q += BLOCK) {
         int64_t r = q;
         if constexpr (FOLD) {
-          r = s.src[q];
+          r = elem<SMALL>(s.src, q);
           r = r >= 0 && r < s.np_src ? r : -1;
         }
-        if (r >= 0) wm = fmaxf(wm, fabsf(static_cast<float>(s.w[r])));
+        if (r >= 0) wm = fmaxf(wm, fabsf(static_cast<float>(elem<SMALL>(s.w, r))));
       }
       for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));
       if (__lane_id() == 0) atomicMax(wbits, __float_as_uint(wm));
@@ -572,21 +588,21 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     // FOLD: particle q of the sorted order is read at src[q] (-1: a slot the
     // sort left inconsistent, which it flagged)
     auto from = [&](int64_t q) -> int64_t {
-      const int64_t r = s.src[q];
+      const int64_t r = elem<SMALL>(s.src, q);
       return r >= 0 && r < s.np_src ? r : -1;
     };
     int64_t n_r = -1;
     if constexpr (FOLD) {
       n_r = pn < pend ? from(pn) : -1;
       if (n_r >= 0) {
-        n_cell = s.cell[n_r];
-        n_w = s.w[n_r];
-        load_particle<T, D>(s, n_r, n_o, n_u);
+        n_cell = elem<SMALL>(s.cell, n_r);
+        n_w = elem<SMALL>(s.w, n_r);
+        load_particle<T, D, SMALL>(s, n_r, n_o, n_u);
       }
     } else if (pn < pend) {
-      n_cell = s.cell[pn];
-      n_w = s.w[pn];
-      load_particle<T, D>(s, pn, n_o, n_u);
+      n_cell = elem<SMALL>(s.cell, pn);
+      n_w = elem<SMALL>(s.w, pn);
+      load_particle<T, D, SMALL>(s, pn, n_o, n_u);
     }
     for (int64_t trip = 0; trip < trips; ++trip, pn += BLOCK) {
       const int32_t p_cell = n_cell;
@@ -597,14 +613,14 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
         have = have && n_r >= 0;
         n_r = pn + BLOCK < pend ? from(pn + BLOCK) : -1;
         if (n_r >= 0) {
-          n_cell = s.cell[n_r];
-          n_w = s.w[n_r];
-          load_particle<T, D>(s, n_r, n_o, n_u);
+          n_cell = elem<SMALL>(s.cell, n_r);
+          n_w = elem<SMALL>(s.w, n_r);
+          load_particle<T, D, SMALL>(s, n_r, n_o, n_u);
         }
       } else if (pn + BLOCK < pend) {
-        n_cell = s.cell[pn + BLOCK];
-        n_w = s.w[pn + BLOCK];
-        load_particle<T, D>(s, pn + BLOCK, n_o, n_u);
+        n_cell = elem<SMALL>(s.cell, pn + BLOCK);
+        n_w = elem<SMALL>(s.w, pn + BLOCK);
+        load_particle<T, D, SMALL>(s, pn + BLOCK, n_o, n_u);
       }
       const int64_t p = pn;
       int c[3] = {0, 0, 0};
@@ -735,22 +751,22 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
 #pragma unroll
         for (int d = 0; d < D; ++d) {
           c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-          off_o[d][p] = on[d];
+          elem<SMALL>(off_o[d], p) = on[d];
         }
-        cell_o[p] = pack(c, g);
-        u_o[0][p] = u[0];
-        u_o[1][p] = u[1];
-        u_o[2][p] = u[2];
-        if (s.open && (c[0] < s.xlo || c[0] >= s.xhi)) w_o[p] = T(0);  // removed at an open face
-        else if (FOLD) w_o[p] = w;
+        elem<SMALL>(cell_o, p) = pack(c, g);
+        elem<SMALL>(u_o[0], p) = u[0];
+        elem<SMALL>(u_o[1], p) = u[1];
+        elem<SMALL>(u_o[2], p) = u[2];
+        if (s.open && (c[0] < s.xlo || c[0] >= s.xhi)) elem<SMALL>(w_o, p) = T(0);  // removed at an open face
+        else if (FOLD) elem<SMALL>(w_o, p) = w;
       } else if (FOLD && have) {  // a straggler or a removed particle moves unchanged
 #pragma unroll
-        for (int d = 0; d < D; ++d) off_o[d][p] = o[d];
-        cell_o[p] = p_cell;
-        u_o[0][p] = u[0];
-        u_o[1][p] = u[1];
-        u_o[2][p] = u[2];
-        w_o[p] = w;
+        for (int d = 0; d < D; ++d) elem<SMALL>(off_o[d], p) = o[d];
+        elem<SMALL>(cell_o, p) = p_cell;
+        elem<SMALL>(u_o[0], p) = u[0];
+        elem<SMALL>(u_o[1], p) = u[1];
+        elem<SMALL>(u_o[2], p) = u[2];
+        elem<SMALL>(w_o, p) = w;
       }
     }
     __syncthreads();
@@ -950,9 +966,13 @@ hipError_t deposit_impl(const pic_ctx &c, const pic_species &sp, const pic_field
 template <typename T, int D, int M, class G, int BLOCK, typename TJ>
 hipError_t launch_tiled_acc(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                             hipStream_t st) {
-  // only 3D launches fold a sort's copy
-  const auto kern = (D == 3 && sa.src) ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3>
-                                       : k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, false>;
+  // only 3D launches fold a sort's copy; 32-bit particle offsets below 2^30 particles
+  const bool fold = D == 3 && sa.src;
+  const bool small = (sa.np > sa.np_src ? sa.np : sa.np_src) < (int64_t(1) << 30);
+  const auto kern = fold ? (small ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3, true>
+                                  : k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3, false>)
+                         : (small ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, false, true>
+                                  : k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, false, false>);
   const size_t lds = c.lds_bytes;
   // granted on every launch (idempotent, and valid for whichever device is current)
   if (lds > 65536) {
