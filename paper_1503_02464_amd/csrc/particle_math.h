@@ -321,6 +321,47 @@ __device__ __forceinline__ void esirkepov_factors(const T o0[3], const int dc[3]
   }
 }
 
+// The same factors for a particle whose nearest node (M = 2) or cell (M = 1)
+// did not change on any axis (the caller knows it): the window is M + 1 nodes
+// from the old nearest node's lower neighbour (M = 2) or the cell (M = 1),
+// and only the first M + 1 entries (M for CDS) are filled, which are all that
+// the FAST accumulation reads.
+template <typename T, int D, int M>
+__device__ __forceinline__ void esirkepov_factors_fast(const T o0[3], const T o1[3], Esirk<T, M> &e) {
+  e.cross = false;
+  e.b[0] = e.b[1] = e.b[2] = 0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    if constexpr (M == 2) {
+      const bool u0 = o0[d] >= T(0.5), u1 = o1[d] >= T(0.5);
+      const T d0 = u0 ? o0[d] - T(1) : o0[d], d1 = u1 ? o1[d] - T(1) : o1[d];
+      e.b[d] = u0 ? 0 : -1;
+      quad_weights<T>(d0, e.S0[d]);
+      const T dd = d1 - d0, sm = T(2) * d0 + dd;
+      e.DS[d][0] = T(-0.5) * dd * (T(1) - sm);
+      e.DS[d][1] = -dd * sm;
+      e.DS[d][2] = T(0.5) * dd * (T(1) + sm);
+    } else {
+      const T dd = o1[d] - o0[d];
+      e.S0[d][0] = T(1) - o0[d];
+      e.S0[d][1] = o0[d];
+      e.DS[d][0] = -dd;
+      e.DS[d][1] = dd;
+    }
+    T run = T(0);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      run += e.DS[d][i];
+      e.CDS[d][i] = run;
+    }
+#pragma unroll
+    for (int i = 0; i <= M; ++i) {
+      e.A[d][i] = e.S0[d][i] + T(0.5) * e.DS[d][i];
+      e.Bf[d][i] = T(0.5) * e.S0[d][i] + e.DS[d][i] * T(1.0 / 3.0);
+    }
+  }
+}
+
 // Esirkepov current of one particle:
 //   J_x(i+1/2) - J_x(i-1/2) = -(q w / dV)(dx/dt) W_x(i), and in 3D
 //   W_x = DS_x (S0_y S0_z + DS_y S0_z / 2 + S0_y DS_z / 2 + DS_y DS_z / 3)

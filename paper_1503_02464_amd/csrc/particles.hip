@@ -703,20 +703,21 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           so[d] = lane_push(to, o[d]);
           sn[d] = lane_push(to, on[d]);
         }
-        const int32_t sk = lane_push(to, fast ? pack_local(lc, dc) : int32_t(0));
+        // the packed local cell (24 bits, so never negative) doubles as the flag
+        const int32_t sk = lane_push(to, fast ? pack_local(lc, dc) : int32_t(-1));
         const T sw = lane_push(to, w);
-        if (lane_push(to, fast ? int32_t(1) : int32_t(0))) {
+        if (sk >= 0) {
           int slc[3], sdc[3];
           unpack_local(sk, slc, sdc);
           Esirk<T, M> e;
-          esirkepov_factors<T, D, M>(so, sdc, sn, e);
+          esirkepov_factors_fast<T, D, M>(so, sn, e);
           const T jc[3] = {sw * tjc[0], sw * tjc[1], sw * tjc[2]};
           esirkepov_accumulate<T, D, M, true>(lj, slc, e, jc, T(0));
         }
       } else {
         if (fast) {
           Esirk<T, M> e;
-          esirkepov_factors<T, D, M>(o, dc, on, e);
+          esirkepov_factors_fast<T, D, M>(o, on, e);
           const T jc[3] = {w * tjc[0], w * tjc[1], w * tjc[2]};
           esirkepov_accumulate<T, D, M, true>(lj, lc, e, jc, w * jz);
         }
