@@ -452,7 +452,8 @@ struct CurrentBox<T, RuntimeGeom, DD> {
 // FOLD: the launch takes over a sort's copy (reads through s.src, writes the
 // *_o arrays); otherwise it updates the particles in place and never touches
 // those pointers, which keeps them out of the registers.
-// SMALL: every particle index of the launch (and of src) is below 2^30.
+// SMALL: every byte offset into a particle array of the launch (the
+// particles it reads, through src or not, and writes) fits in 32 bits.
 template <typename T, int D, int M, class G, int BLOCK, typename TJ, bool FOLD, bool SMALL>
 __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                               GlobalCurrent<T> gj, TileArgs t, int32_t *flags) {
@@ -967,9 +968,11 @@ hipError_t deposit_impl(const pic_ctx &c, const pic_species &sp, const pic_field
 template <typename T, int D, int M, class G, int BLOCK, typename TJ>
 hipError_t launch_tiled_acc(const pic_ctx &c, const SpeciesArgs<T> &sa, const pic_fields &f, const TileArgs &t,
                             hipStream_t st) {
-  // only 3D launches fold a sort's copy; 32-bit particle offsets below 2^30 particles
+  // only 3D launches fold a sort's copy; 32-bit byte offsets while every
+  // particle array (elements of sizeof(T) at most) spans at most 2^32 bytes
   const bool fold = D == 3 && sa.src;
-  const bool small = (sa.np > sa.np_src ? sa.np : sa.np_src) < (int64_t(1) << 30);
+  const int64_t nmax = sa.np > sa.np_src ? sa.np : sa.np_src;
+  const bool small = nmax * static_cast<int64_t>(sizeof(T)) <= (int64_t(1) << 32);
   const auto kern = fold ? (small ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3, true>
                                   : k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, D == 3, false>)
                          : (small ? k_push_deposit_tiled<T, D, M, G, BLOCK, TJ, false, true>
