@@ -374,6 +374,11 @@ class Simulation:
         mx, my, mz = self.box_shape(b)
         shape = (len(grids), mz, my, mx)
         dtype = grids[0].dtype
+        for t in grids:  # the library reads n0 n1 n2 elements of one size from each pointer
+            if t.dtype != dtype or t.numel() != self.ncells or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("grids must be contiguous device tensors of ncells elements of one dtype")
+        if out is not None and (out.dtype != dtype or out.numel() < len(grids) * mx * my * mz or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous tensor of the grids' dtype holding every extracted value")
         if out is None:
             out = torch.empty(shape, dtype=dtype, device=self.device)
         arr = (ctypes.c_void_p * len(grids))(*[_ptr(g) for g in grids])
@@ -390,7 +395,10 @@ class Simulation:
         number selected goes to count (a device int64 tensor of one element).
         Enqueued on the current stream, not synchronised."""
         rec = self.dims + 4
-        assert out.dtype == self.dtype and out.numel() % rec == 0 and count.dtype == torch.int64
+        if out.dtype != self.dtype or out.numel() % rec != 0 or not out.is_contiguous() or out.device != self.device:
+            raise ValueError(f"out must be a contiguous device tensor of records of {rec} {self.dtype} values")
+        if count.dtype != torch.int64 or count.numel() < 1 or count.device != self.device:
+            raise ValueError("count must be a device int64 tensor")
         self._call(self.lib.pic_extract_particles(self.ctx, ctypes.byref(s.struct), ctypes.byref(cells), int(every),
                                                   ctypes.c_void_p(_ptr(out)), out.numel() // rec,
                                                   ctypes.c_void_p(_ptr(count)), ctypes.c_void_p(_stream())),
