@@ -375,7 +375,7 @@ class Simulation:
         shape = (len(grids), mz, my, mx)
         dtype = grids[0].dtype
         for t in grids:  # the library reads n0 n1 n2 elements of one size from each pointer
-            if t.dtype != dtype or t.numel() != self.ncells or not t.is_contiguous() or t.device != self.device:
+            if t.dtype != dtype or t.numel() != self.ncells or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError("grids must be contiguous device tensors of ncells elements of one dtype")
         if out is not None and (out.dtype != dtype or out.numel() < len(grids) * mx * my * mz or not out.is_contiguous()):
             raise ValueError("out must be a contiguous tensor of the grids' dtype holding every extracted value")
@@ -395,9 +395,9 @@ class Simulation:
         number selected goes to count (a device int64 tensor of one element).
         Enqueued on the current stream, not synchronised."""
         rec = self.dims + 4
-        if out.dtype != self.dtype or out.numel() % rec != 0 or not out.is_contiguous() or out.device != self.device:
+        if out.dtype != self.dtype or out.numel() % rec != 0 or not out.is_contiguous() or not out.is_cuda:
             raise ValueError(f"out must be a contiguous device tensor of records of {rec} {self.dtype} values")
-        if count.dtype != torch.int64 or count.numel() < 1 or count.device != self.device:
+        if count.dtype != torch.int64 or count.numel() < 1 or not count.is_cuda:
             raise ValueError("count must be a device int64 tensor")
         self._call(self.lib.pic_extract_particles(self.ctx, ctypes.byref(s.struct), ctypes.byref(cells), int(every),
                                                   ctypes.c_void_p(_ptr(out)), out.numel() // rec,
