@@ -1062,6 +1062,8 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   } else {
     if (L[0] == 16 && L[1] == 16 && sl == 1 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 1>::FX)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sa, f, t, st);
+    else if (L[0] == 8 && L[1] == 8 && sl == 1 && c.rf[0] == FixedGeom<D, M, 8, 8, 1, 1>::FX)  // dense foils
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 1, 1>, 256>(c, sa, f, t, st);
     else if (L[0] == 16 && L[1] == 16 && sl == 2 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 2>::FX)  // the rollout
       e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sa, f, t, st);
     else

@@ -2,7 +2,7 @@
 ions, quadratic shape) on the GPU against the FP64 oracle.
 
 Full size, in the launch configuration of their workloads (FP32 state,
-16x16 tiles in 2D, 8x8x8 in 3D, slack 1, sort every 4 steps): two steps from
+8x8 tiles in 2D, 8x8x8 in 3D, slack 1, sort every 4 steps): two steps from
 the seeded foil with small seeded fields added everywhere (so that the cold
 foil moves at once); the oracle checks sampled particles of the second step
 (no re-sort in between, so indices match) and E, B everywhere from the GPU's
