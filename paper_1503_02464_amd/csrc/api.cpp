@@ -239,9 +239,12 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
     delete c;
     return PIC_EINVAL;
   }
-  // the wide-window list takes what is left, in multiples of 64 entries
+  // the wide-window list takes what is left, in multiples of 64 entries;
+  // where the boxes are small (2D 8x8 tiles of a dense foil) it is twice as
+  // long, for the many hot electrons such a tile holds
   const size_t entry = 8 * c->elem + 4;
   int cap = c->elem == 4 ? pic::kCrossCapF32 : pic::kCrossCapF64;
+  if (boxes < 16 * 1024) cap *= 2;
   const size_t room = (pic::kLdsLimit - boxes - pic::cross_list_bytes(c->elem, 0)) / entry;
   if (static_cast<size_t>(cap) > room) cap = static_cast<int>(room / 64 * 64);
   c->cross_cap = cap;

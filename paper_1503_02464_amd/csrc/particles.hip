@@ -741,11 +741,12 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
             xw[k] = w;
             xw[CAP + k] = jz;
             xk[k] = pack_local(lc, dc);
-          } else {  // list full: deposit here
-            Esirk<T, M> e;
-            esirkepov_factors<T, D, M>(o, dc, on, e);
+          } else {  // list full: deposit here, in the drain's form
             const T jc[3] = {w * tjc[0], w * tjc[1], w * tjc[2]};
-            esirkepov_accumulate<T, D, M, false>(lj, lc, e, jc, w * jz);
+            if constexpr (D == 3)
+              esirkepov_rotated<T, M>(jl, geo.JX, geo.JXY, geo.JVOL, geo.JLO, lc, o, dc, on, jc);
+            else
+              esirkepov_rotated_2d<T, M>(jl, geo.JX, geo.JVOL, geo.JLO, lc, o, dc, on, jc, w * jz);
           }
         }
       }

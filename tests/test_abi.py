@@ -74,6 +74,12 @@ def test_valid_init_and_queries(lib):
         assert st2 == L.PIC_OK
         assert lib.pic_tile_lds_bytes(c2) == want, (prec, tile)
         lib.pic_destroy(c2)
+    # 2D 8x8 tiles (dense foils): fields 14 x 13, current 15 x 15, both under 16 KB, so the
+    # wide-window list is twice as long (1024 entries)
+    st2, c2 = init(lib, params(dims=2, n=(64, 64, 1), dx=(0.05, 0.05, 0.0), tile=(8, 8, 1)))
+    assert st2 == L.PIC_OK
+    assert lib.pic_tile_lds_bytes(c2) == 14 * 13 * 6 * 4 + 15 * 15 * 3 * 8 + 1024 * 36 + 16
+    lib.pic_destroy(c2)
     assert lib.pic_step_count(ctx) == 0
     lib.pic_destroy(ctx)
 
