@@ -1052,7 +1052,11 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   if (e != hipSuccess) return e;
   const int *L = c.p.tile;
   const int sl = c.p.slack;
-  constexpr int BIG = sizeof(T) == 4 ? 1024 : 512;  // threads per workgroup of the fixed-shape kernels
+  // threads per workgroup of the fixed-shape kernels: in 3D 16 waves in FP32
+  // and 12 in FP64, whose kernel needs up to 168 registers (3 waves per SIMD);
+  // in 2D 16 waves in FP32 and 8 in FP64
+  constexpr int BIG = sizeof(T) == 4 ? 1024 : 768;
+  constexpr int DENSE = sizeof(T) == 4 ? 1024 : 512;
   if constexpr (D == 3) {
     if (sizeof(T) == 4 && L[0] == 8 && L[1] == 8 && L[2] == 8 && sl == 1 && c.rf[0] == FixedGeom<D, M, 8, 8, 8, 1>::FX)
       e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 8, 1>, BIG>(c, sa, f, t, st);
@@ -1062,11 +1066,11 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   } else {
     if (L[0] == 16 && L[1] == 16 && sl == 1 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 1>::FX)
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, 256>(c, sa, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 1>, DENSE>(c, sa, f, t, st);
     else if (L[0] == 8 && L[1] == 8 && sl == 1 && c.rf[0] == FixedGeom<D, M, 8, 8, 1, 1>::FX)  // dense foils
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 1, 1>, 256>(c, sa, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 8, 8, 1, 1>, DENSE>(c, sa, f, t, st);
     else if (L[0] == 16 && L[1] == 16 && sl == 2 && c.rf[0] == FixedGeom<D, M, 16, 16, 1, 2>::FX)  // the rollout
-      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, 256>(c, sa, f, t, st);
+      e = launch_tiled<T, D, M, FixedGeom<D, M, 16, 16, 1, 2>, DENSE>(c, sa, f, t, st);
     else
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   }

@@ -95,6 +95,42 @@ def test_wide_list_overflow(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_list_overflow_2d(prec):
+    """The same in 2D on the 8x8 tiles of dense foils, whose small boxes leave
+    room for a list twice as long (1024 entries in FP32, 512 in FP64): 6000
+    particles of one tile cross a half-cell in x, most of them in y too, with
+    out-of-plane momentum (the J_z of the in-place deposit)."""
+    g = grid(2, (16, 16), dx=0.05, cfl=0.7, order=2)
+    r = inputs.rng(630)
+    npart = 6000
+    sp = {"q": -1.0, "m": 1.0, "cell": np.zeros((3, npart), np.int32), "off": np.zeros((3, npart)),
+          "u": np.zeros((3, npart)), "w": np.ones(npart)}
+    sp["cell"][0] = r.integers(0, 8, npart)
+    sp["cell"][1] = r.integers(0, 8, npart)
+    sp["off"][0] = 0.5 - r.uniform(0.001, 0.05, npart)  # just below the half-cell, heading +x
+    sp["off"][1] = r.random(npart)
+    sp["u"][0] = r.uniform(0.6, 1.5, npart)
+    sp["u"][1] = r.normal(0, 0.6, npart)
+    sp["u"][2] = r.normal(0, 0.5, npart)
+    sp = unique_weights(sp, 631, scale=1e-3)
+    f = inputs.random_fields(g.ncells, 0.05, 632)
+    if prec == "fp32":
+        sp, f = inputs.round_f32(sp), inputs.round_fields_f32(f)
+    s = make_sim(g, prec, (8, 8), slack=1, sort_every=4, max_particles=npart)
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(1)
+    s.check()
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    crossed = np.sum((ref_sp["off"][0] >= 0.5) | (ref_sp["cell"][0] != sp["cell"][0]))
+    assert crossed > 4 * 1024, crossed
+    compare_species(g, prec, s.get_species(h), ref_sp, "wide overflow 2D")
+    compare_fields(prec, s.get_fields(), ref_f, what="wide overflow 2D")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_more_tiles_than_workgroups(prec):
     """More non-empty tiles than the device runs workgroups of the production
     tile shape at once, so workgroups take further tiles from the per-XCD
