@@ -160,15 +160,16 @@ def laser_foil_2d(scale: int = 1) -> LaserFoil:
     open x, periodic y; foil 0.5 lambda at 50 n_c, 64 ppc per species, cold;
     a0 = 5, waist 4 lambda, 10 cycles; quadratic shape, 2000 steps; 8x8
     tiles (the foil is 20 cells thick: 16x16 tiles left a quarter of the
-    CUs busy).  ``scale`` divides the box, the foil position and thickness
-    and the spot."""
+    CUs busy) and 64 sort levels (128, twice the particles per cell, only
+    lengthen the sort's scans over tiles x levels).  ``scale`` divides the
+    box, the foil position and thickness and the spot."""
     lam = 2 * math.pi
     dx = lam / 40
     x0 = 400 // scale
     return LaserFoil(f"laser-foil-2d3v-{2048 // scale}x{1024 // scale}-64ppc-quadratic", 2,
                      (2048 // scale, 1024 // scale, 1), (dx, dx, 1.0), 0.98, 2, 2000, (x0, x0 + max(20 // scale, 2)),
                      50.0, 64, 0.0, 0.0, 5.0, 4 * lam / scale, 10 * lam, tile=(8, 8, 1), seed=1001,
-                     sort_levels=128)
+                     sort_levels=64)
 
 
 def laser_foil_3d(scale: int = 1) -> LaserFoil:
