@@ -357,10 +357,8 @@ pic_status pic_deposit(pic_ctx *c, const pic_species *sp, pic_fields *f, void *s
 pic_status pic_zero_current(pic_ctx *c, pic_fields *f, void *stream) {
   if (!c) return PIC_EINVAL;
   if (!fields_ok(f)) return fail(c, PIC_EINVAL, "bad fields");
-  for (int d = 0; d < 3; ++d) {
-    hipError_t e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return hip_fail(c, e, "zero_current");
-  }
+  hipError_t e = pic::launch_fill_zero_n(f->J, 3, c->ncells, c->elem, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(c, e, "zero_current");
   return PIC_OK;
 }
 
@@ -430,7 +428,7 @@ pic_status pic_step(pic_ctx *c, pic_species *sp, int32_t nspecies, pic_fields *f
     const bool cadence = c->p.sort_every > 0 && (c->step % c->p.sort_every) == 0;
     {
       PhaseTimer t(c, s, pic::kPhaseZero);
-      for (int d = 0; d < 3 && e == hipSuccess; ++d) e = pic::launch_fill_zero(f->J[d], c->ncells, c->elem, s);
+      e = pic::launch_fill_zero_n(f->J, 3, c->ncells, c->elem, s);
       if (e == hipSuccess && c->has_laser) e = pic::launch_laser(*c, *f, (c->step + 0.5) * c->p.dt, s);
       if (e != hipSuccess) return hip_fail(c, e, "zero_current");
     }

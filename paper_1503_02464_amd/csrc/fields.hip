@@ -243,6 +243,18 @@ __global__ void __launch_bounds__(256) k_fill_zero(T *p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = T(0);
 }
 
+// Up to kFillArrays arrays of n elements in one launch (grid y picks the array).
+template <typename T>
+struct FillArrays {
+  T *p[kFillArrays];
+};
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_zero_n(FillArrays<T> a, int64_t n) {
+  T *p = a.p[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) p[i] = T(0);
+}
+
 template <typename T>
 Yee<T> yee_args(const pic_ctx &c, const pic_fields &f, double frac) {
   Yee<T> a{};
@@ -426,6 +438,26 @@ hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s) {
                        static_cast<float *>(ptr), n);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_n(void *const *ptrs, int count, int64_t n, size_t elem, hipStream_t s) {
+  if (count < 1 || count > kFillArrays) return hipErrorInvalidValue;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;  // writes stream best with many workgroups in flight
+  const dim3 grid(static_cast<unsigned>(blocks), static_cast<unsigned>(count));
+  if (elem == 8) {
+    FillArrays<double> a{};
+    for (int i = 0; i < count; ++i) a.p[i] = static_cast<double *>(ptrs[i]);
+    hipLaunchKernelGGL(k_fill_zero_n<double>, grid, dim3(256), 0, s, a, n);
+  } else if (elem == 4) {
+    FillArrays<float> a{};
+    for (int i = 0; i < count; ++i) a.p[i] = static_cast<float *>(ptrs[i]);
+    hipLaunchKernelGGL(k_fill_zero_n<float>, grid, dim3(256), 0, s, a, n);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -144,6 +144,9 @@ hipError_t launch_deposit(const pic_ctx &c, const pic_species &sp, const pic_fie
 hipError_t launch_push_deposit_tiled(const pic_ctx &c, pic_species &sp, const pic_fields &f, hipStream_t s,
                                      const int32_t *src = nullptr, int64_t np_src = 0);
 hipError_t launch_fill_zero(void *ptr, int64_t n, size_t elem, hipStream_t s);
+// Zero count (1..kFillArrays) arrays of n elements each in one launch.
+constexpr int kFillArrays = 4;
+hipError_t launch_fill_zero_n(void *const *ptrs, int count, int64_t n, size_t elem, hipStream_t s);
 // Open x faces: save = true keeps E_y, E_z^n next to the faces (before the E
 // update), save = false applies the Mur update to the faces (after it).
 hipError_t launch_mur(const pic_ctx &c, const pic_fields &f, bool save, hipStream_t s);

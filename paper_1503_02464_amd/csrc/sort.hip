@@ -628,8 +628,8 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
   const int64_t nb = c.ntiles * c.levels + 1;
   int32_t *stay = c.wsp<int32_t>(c.ws.stay_count);
   int32_t *arrive = c.wsp<int32_t>(c.ws.arrive_count);
-  hipError_t e = launch_fill_zero(stay, nb, 4, s);
-  if (e == hipSuccess) e = launch_fill_zero(arrive, nb, 4, s);
+  void *const counts[2] = {stay, arrive};
+  hipError_t e = launch_fill_zero_n(counts, 2, nb, 4, s);
   if (e != hipSuccess) return e;
   // The previous sort's tile runs (and its bucket starts, kept in the
   // species' slot) stay valid while the particle set is the one this context
