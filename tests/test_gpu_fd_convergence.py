@@ -65,5 +65,5 @@ def test_fd_error_vanishes_with_the_window_changes():
     assert all(a >= b for a, b in zip(counts, counts[1:])), rows  # fewer changes as eps shrinks
     for eps, changed, err in rows:
         if changed == 0:
-            assert err <= 1e-4, (eps, err)  # smooth: the benchmark spec's gate holds
+            assert err <= 1e-4, (eps, err)  # smooth: the 1e-4 finite-difference gate holds
     assert max(r[2] for r in rows if r[1] > 0) > max(r[2] for r in rows if r[1] == 0), rows
