@@ -278,6 +278,8 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.bucket_start = take(static_cast<size_t>(pic::kMaxSpecies) * (nbuckets + 1) * 4);
   w.scan_partials = take(static_cast<size_t>(pic::sort_scan_blocks(nbuckets)) * 8);
   w.live_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
+  w.dense_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
+  w.sparse_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
   w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
   w.result = take(16 * 8);
   w.rho = take(static_cast<size_t>(ncells) * 8);

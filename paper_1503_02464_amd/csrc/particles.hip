@@ -818,42 +818,65 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
   }
 }
 
-// The particles a tiled launch left outside their LDS box: full step with
-// fields and current in HBM.
+// One particle's full step with the fields and current in HBM, updated in
+// place (particle p of the species' arrays): gather, Boris, move, deposit
+// with global atomics, removal at an open face.
+template <typename T, int D, int M>
+__device__ __forceinline__ void push_hbm(const SpeciesArgs<T> &s, const GridArgs &g, const GlobalFields<T> &gf,
+                                         const GlobalCurrent<T> &gj, int64_t p, int32_t *flags) {
+  const T w = s.w[p];
+  if (s.open && w == T(0)) return;  // removed at an open face
+  int c[3];
+  unpack(s.cell[p], g, c);
+  T o[3], u[3];
+  load_particle<T, D>(s, p, o, u);
+  T eb[6];
+  gather_eb<T, D, M>(gf, c, o, eb);
+  boris<T>(u, eb, s.h);
+  const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+  T on[3] = {T(0), T(0), T(0)};
+  int dc[3] = {0, 0, 0};
+  const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
+  if (!ok) atomicOr(&flags[0], kFlagCross);
+  const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
+  const T jz = D == 2 ? w * s.jz * u[2] * ig : T(0);
+  if (ok) deposit<T, D, M>(gj, c, o, dc, on, jc, jz);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    c[d] = wrap_near(c[d] + dc[d], g.n[d]);
+    s.off[d][p] = on[d];
+  }
+  s.cell[p] = pack(c, g);
+  s.u[0][p] = u[0];
+  s.u[1][p] = u[1];
+  s.u[2][p] = u[2];
+  absorb_if_out(s, p, c[0]);
+}
+
+// The particles a tiled launch left outside their LDS box, then (when few is
+// given) every particle of the tiles the launch skipped for having few
+// particles, one wavefront per tile: full step with fields and current in HBM.
 template <typename T, int D, int M>
 __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                     GlobalCurrent<T> gj, const int32_t *count, const int32_t *list,
+                                                    const int32_t *few, const int32_t *tile_start, int64_t ntiles,
                                                     int32_t *flags) {
   const int64_t n = *count;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = list[k];
-    const T w = s.w[p];
-    if (s.open && w == T(0)) continue;  // removed at an open face
-    int c[3];
-    unpack(s.cell[p], g, c);
-    T o[3], u[3];
-    load_particle<T, D>(s, p, o, u);
-    T eb[6];
-    gather_eb<T, D, M>(gf, c, o, eb);
-    boris<T>(u, eb, s.h);
-    const T ig = rsqrt_t<T>(T(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    T on[3] = {T(0), T(0), T(0)};
-    int dc[3] = {0, 0, 0};
-    const bool ok = move<T, D>(u, ig, s.dtdx, o, on, dc);
-    if (!ok) atomicOr(&flags[0], kFlagCross);
-    const T jc[3] = {w * s.jc[0], w * s.jc[1], w * s.jc[2]};
-    const T jz = D == 2 ? w * s.jz * u[2] * ig : T(0);
-    if (ok) deposit<T, D, M>(gj, c, o, dc, on, jc, jz);
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      c[d] = wrap_near(c[d] + dc[d], g.n[d]);
-      s.off[d][p] = on[d];
-    }
-    s.cell[p] = pack(c, g);
-    s.u[0][p] = u[0];
-    s.u[1][p] = u[1];
-    s.u[2][p] = u[2];
-    absorb_if_out(s, p, c[0]);
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    push_hbm<T, D, M>(s, g, gf, gj, list[k], flags);
+  if (!few) return;
+  int64_t nfew = few[ntiles];
+  nfew = nfew < 0 ? 0 : (nfew > ntiles ? ntiles : nfew);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+  const int lane = __lane_id();
+  for (int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64; i < nfew; i += waves) {
+    const int64_t tile = few[i];
+    if (tile < 0 || tile >= ntiles) continue;
+    // clamp to the species, as the fused kernel does
+    int64_t pbeg = tile_start[tile], pend = tile_start[tile + 1];
+    pbeg = pbeg < 0 ? 0 : (pbeg > s.np ? s.np : pbeg);
+    pend = pend > s.np ? s.np : pend;
+    for (int64_t q = pbeg + lane; q < pend; q += 64) push_hbm<T, D, M>(s, g, gf, gj, q, flags);
   }
 }
 
@@ -1042,7 +1065,10 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   t.slack = c.p.slack;
   t.jxy = c.jxy;
   t.remap = c.ntiles >= 64 ? 1 : 0;
-  t.live = live_tiles(c, sp);
+  // a launch that folds a sort's copy takes every non-empty tile; the in-place
+  // ones leave the tiles with few particles to the straggler kernel
+  t.live = src ? live_tiles(c, sp) : dense_tiles(c, sp);
+  const int32_t *few = src ? nullptr : sparse_tiles(c, sp);
   t.ntiles = c.ntiles;
   t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
   t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
@@ -1086,7 +1112,7 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   }
   hipLaunchKernelGGL((k_stragglers<T, D, M>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
                      species_args<T>(c, sp), grid_args(c), global_fields<T>(c, f), global_current<T>(c, f),
-                     t.stray_count, t.stray_list, c.wsp<int32_t>(c.ws.flags));
+                     t.stray_count, t.stray_list, few, sp.tile_start, c.ntiles, c.wsp<int32_t>(c.ws.flags));
   return hipGetLastError();
 }
 

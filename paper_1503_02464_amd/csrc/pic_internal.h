@@ -60,6 +60,8 @@ struct Workspace {
   size_t scan_partials = 0;  // int64[scan blocks]
   size_t live_tiles = 0;     // int32[kMaxSpecies][ntiles + 1]: per species slot, the tiles its last sort
                              // left non-empty, in tile order, then their count
+  size_t dense_tiles = 0;    // int32[kMaxSpecies][ntiles + 1]: of those, the ones with kSparseTile particles or more
+  size_t sparse_tiles = 0;   // int32[kMaxSpecies][ntiles + 1]: and the others (3D; empty in 2D)
   size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
   size_t result = 0;      // double[16]
   size_t rho = 0;         // double[ncells]
@@ -176,6 +178,13 @@ void swap_sets(pic_species &sp);
 // The non-empty tiles of a species' last sort (list, count at [ntiles]), or
 // null when this context has not sorted that species.
 const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp);
+// A 3D tile that its last sort left with fewer than kSparseTile particles is
+// not staged by the in-place fused launches: the straggler kernel steps its
+// particles against the fields and current in HBM.  These return the two
+// parts of the live list (same layout), or null where live_tiles does.
+constexpr int kSparseTile = 32;
+const int32_t *dense_tiles(const pic_ctx &c, const pic_species &sp);
+const int32_t *sparse_tiles(const pic_ctx &c, const pic_species &sp);
 
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();

@@ -461,21 +461,38 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_apply(const int32_t *ca, co
 }
 
 // The tiles left non-empty, in tile order, and their count at [ntiles]: each
-// thread counts a contiguous chunk, one block scan places the chunks.
-__global__ void __launch_bounds__(kScanBlock) k_list_tiles(const int32_t *tile_start, int64_t ntiles,
-                                                          int32_t *live) {
+// thread counts a contiguous chunk, one block scan places the chunks.  The
+// same for the non-empty tiles with at least `sparse` particles (dense) and
+// with fewer (sparse); sparse = 0 makes every live tile dense.
+__global__ void __launch_bounds__(kScanBlock) k_list_tiles(const int32_t *tile_start, int64_t ntiles, int32_t sparse,
+                                                          int32_t *live, int32_t *dense, int32_t *few) {
   __shared__ int64_t sh[kScanBlock];
   const int64_t per = (ntiles + kScanBlock - 1) / kScanBlock;
   const int64_t a = threadIdx.x * per;
   const int64_t e = a + per < ntiles ? a + per : ntiles;
-  int64_t cnt = 0;
+  int64_t cnt = 0, cnt_few = 0;
 #pragma unroll 8
-  for (int64_t t = a; t < e; ++t) cnt += tile_start[t + 1] > tile_start[t] ? 1 : 0;
-  int64_t total;
+  for (int64_t t = a; t < e; ++t) {
+    const int32_t n = tile_start[t + 1] - tile_start[t];
+    cnt += n > 0 ? 1 : 0;
+    cnt_few += n > 0 && n < sparse ? 1 : 0;
+  }
+  int64_t total, total_few;
   int64_t pos = block_exclusive_scan(cnt, sh, total);
-  for (int64_t t = a; t < e; ++t)
-    if (tile_start[t + 1] > tile_start[t]) live[pos++] = static_cast<int32_t>(t);
-  if (threadIdx.x == 0) live[ntiles] = static_cast<int32_t>(total);
+  __syncthreads();  // sh is reused
+  int64_t pos_few = block_exclusive_scan(cnt_few, sh, total_few);
+  int64_t pos_dense = pos - pos_few;
+  for (int64_t t = a; t < e; ++t) {
+    const int32_t n = tile_start[t + 1] - tile_start[t];
+    if (n > 0) live[pos++] = static_cast<int32_t>(t);
+    if (n > 0 && n < sparse) few[pos_few++] = static_cast<int32_t>(t);
+    else if (n > 0) dense[pos_dense++] = static_cast<int32_t>(t);
+  }
+  if (threadIdx.x == 0) {
+    live[ntiles] = static_cast<int32_t>(total);
+    dense[ntiles] = static_cast<int32_t>(total - total_few);
+    few[ntiles] = static_cast<int32_t>(total_few);
+  }
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin.  The copy passes launch a
@@ -671,6 +688,8 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
   }
   int32_t *start = c.wsp<int32_t>(c.ws.bucket_start) + static_cast<size_t>(slot) * (nb + 1);
   int32_t *live = c.wsp<int32_t>(c.ws.live_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
+  int32_t *dense = c.wsp<int32_t>(c.ws.dense_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
+  int32_t *few = c.wsp<int32_t>(c.ws.sparse_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
   if (sp.np > 0) {
     SortGeom g{};
     g.bits0 = c.bits[0];
@@ -698,7 +717,8 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
   hipLaunchKernelGGL(k_scan_partials_top, dim3(1), dim3(kScanBlock), 0, s, partials, nblk);
   hipLaunchKernelGGL(k_scan_apply, dim3(static_cast<unsigned>(nblk)), dim3(kScanBlock), 0, s, stay, arrive, nb,
                      partials, c.levels, start, sp.tile_start, c.ntiles);
-  hipLaunchKernelGGL(k_list_tiles, dim3(1), dim3(kScanBlock), 0, s, sp.tile_start, c.ntiles, live);
+  hipLaunchKernelGGL(k_list_tiles, dim3(1), dim3(kScanBlock), 0, s, sp.tile_start, c.ntiles,
+                     c.p.dims == 3 ? kSparseTile : 0, live, dense, few);
   const bool copy = fold_src == nullptr || sp.np == 0;
   if (sp.np > 0) {
     const bool f64 = c.p.precision == PIC_FP64;
@@ -748,11 +768,17 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
   return hipSuccess;
 }
 
-const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp) {
+namespace {
+const int32_t *tile_list(const pic_ctx &c, const pic_species &sp, size_t base) {
   for (size_t i = 0; i < c.sorted_runs.size(); ++i)
     if (c.sorted_runs[i].first == sp.tile_start && c.sorted_runs[i].second == sp.np)
-      return c.wsp<int32_t>(c.ws.live_tiles) + i * (c.ntiles + 1);
+      return c.wsp<int32_t>(base) + i * (c.ntiles + 1);
   return nullptr;
 }
+}  // namespace
+
+const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp) { return tile_list(c, sp, c.ws.live_tiles); }
+const int32_t *dense_tiles(const pic_ctx &c, const pic_species &sp) { return tile_list(c, sp, c.ws.dense_tiles); }
+const int32_t *sparse_tiles(const pic_ctx &c, const pic_species &sp) { return tile_list(c, sp, c.ws.sparse_tiles); }
 
 }  // namespace pic

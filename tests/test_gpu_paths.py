@@ -1,9 +1,10 @@
 """Paths of the fused kernel that the uniform workloads rarely take, against
 the FP64 oracle: particles that drift out of their tile's slack between
 sorts (the HBM straggler path), more window-changing particles in one tile
-than its LDS list holds (deposited in place), and more non-empty tiles than
-resident workgroups (the per-XCD tile queues).  FP64 to 1e-12; FP32 one step
-from an FP32-representable state (gpu_helpers.TOL)."""
+than its LDS list holds (deposited in place), more non-empty tiles than
+resident workgroups (the per-XCD tile queues), and 3D tiles with too few
+particles to stage (stepped by the straggler kernel).  FP64 to 1e-12; FP32
+one step from an FP32-representable state (gpu_helpers.TOL)."""
 import numpy as np
 import pytest
 
@@ -262,4 +263,43 @@ def test_crossing_particles_on_one_two_three_axes(prec, dims, order):
     assert min(counts[1:]) >= 20, counts
     compare_species(g, prec, s.get_species(h), ref_sp, f"crossers {counts}")
     compare_fields(prec, s.get_fields(), ref_f, what=f"crossers {counts}")
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sparse_tiles(prec):
+    """Half the 3D box dense (256 particles per tile), the other half with a
+    few particles per tile, some in no tile at all: the in-place launches
+    leave the sparse tiles to the straggler kernel, the launches that fold a
+    sort's copy take every tile.  FP64: four steps (two sorts) against four
+    oracle steps; FP32: an in-place step after a sort against one oracle step
+    from the GPU's state."""
+    g = grid(3, (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    r = inputs.rng(640)
+    dense = inputs.uniform_plasma((8, 16, 8), 3, 2, 0.05, 1.0, 641)  # x < 8: 2048 particles over 8 tiles
+    nsp = 37  # x >= 8: a few particles in each of some of the 8 tiles there
+    cell = np.concatenate([dense["cell"], np.stack([r.integers(8, 16, nsp), r.integers(0, 16, nsp),
+                                                    r.integers(0, 8, nsp)]).astype(np.int32)], axis=1)
+    npart = cell.shape[1]
+    sp = {"q": -1.0, "m": 1.0, "cell": cell, "off": r.random((3, npart)), "u": r.normal(0, 0.05, (3, npart)),
+          "w": np.ones(npart)}
+    sp = unique_weights(sp, 642, scale=0.05 ** 3 / 2)
+    f = inputs.random_fields(g.ncells, 0.1, 643)
+    if prec == "fp32":
+        sp, f = inputs.round_f32(sp), inputs.round_fields_f32(f)
+    s = make_sim(g, prec, (8, 4, 4), slack=1, sort_every=2, max_particles=npart)
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    for n in range(4):  # steps 0 and 2 sort (and fold the copy), 1 and 3 run in place
+        if prec == "fp32" and n == 3:
+            ref_sp, ref_f = gpu_state(s, h)
+            ref_sp["q"], ref_sp["m"] = sp["q"], sp["m"]
+            ref_f["J"] = np.zeros_like(ref_f["J"])
+        s.step(1)
+        if prec == "fp64" or n == 3:
+            assert O.step(g, ref_f, [ref_sp]) == 0
+    s.check()
+    compare_species(g, prec, s.get_species(h), ref_sp, "sparse tiles")
+    compare_fields(prec, s.get_fields(), ref_f, what="sparse tiles")
     s.close()
