@@ -88,6 +88,12 @@ enum { PIC_FP32 = 0, PIC_FP64 = 1 };
  *     truncation is below 2^-30 of the bound per contribution, below the FP32
  *     rounding of the largest contributions.  Integer LDS atomics cost about
  *     half as much as double ones on gfx950 when lanes collide on banks.
+ *     w_max is found by the first fused push after each sort of the species
+ *     and kept per tile in the workspace for the pushes that follow; a
+ *     particle whose |w| has grown past its tile's w_max since then takes the
+ *     HBM path (global gather and atomics), so the bound always holds.
+ *     Weights that shrink a lot without a sort only coarsen the truncation
+ *     relative to the new contributions; sort again after such a change.
  *   FP32: single-precision LDS atomics (accepted for an FP32 state; slow on
  *     gfx950, where the LDS unit serialises them lane by lane).
  *   AUTO (the default): FIX64 for an FP32 state, FP64 for an FP64 state. */

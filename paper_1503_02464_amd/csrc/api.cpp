@@ -280,6 +280,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.live_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
   w.dense_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
   w.sparse_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * (c->ntiles + 1) * 4);
+  w.wmax_tiles = take(static_cast<size_t>(pic::kMaxSpecies) * c->ntiles * 4);
   w.partials = take(static_cast<size_t>(pic::kDiagSlots) * pic::kMaxSpecies * pic::kDiagBlocks * 8);
   w.result = take(16 * 8);
   w.rho = take(static_cast<size_t>(ncells) * 8);
@@ -326,6 +327,10 @@ pic_status pic_set_workspace(pic_ctx *c, void *ptr, size_t bytes) {
   c->wsbytes = bytes;
   c->diag_step = -1;
   c->pending_cell = nullptr;
+  // the tile lists, bucket starts and weight bounds of earlier sorts lived in
+  // the previous workspace
+  c->sorted_runs.clear();
+  for (int i = 0; i < pic::kMaxSpecies; ++i) c->wmax_known[i] = false;
   hipError_t e = hipMemset(c->wsptr + c->ws.flags, 0, 64 * sizeof(int32_t));
   if (e != hipSuccess) return hip_fail(c, e, "clearing workspace flags");
   return PIC_OK;

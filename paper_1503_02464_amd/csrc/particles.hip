@@ -368,6 +368,8 @@ struct TileArgs {
   int32_t *stray_list;
   int32_t *queue;          // [8]: next item of each XCD's range, zero at launch
   int cross_cap;           // entries of the LDS list of wide-window particles
+  uint32_t *wcache;        // [ntiles]: per tile, the bits of its largest |w| (fixed-point current)
+  int wmode;               // 0: find each tile's bound; 1: find and store it in wcache; 2: take it from wcache
 };
 
 __device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
@@ -552,8 +554,13 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
     if (once) stage(near_wrap);
     else stage(full_wrap);
     // the tile's largest |w| sets the fixed-point scale of its current box
-    // (the main loop then reads the weights again, from the L2)
+    // (the main loop then reads the weights again, from the L2); after the
+    // first launch since a sort it comes from the cache of that launch, and a
+    // particle heavier than it (its weight changed since) takes the HBM path
     if constexpr (kFixed) {
+      if (t.wmode == 2) {
+        if (threadIdx.x == 0) *wbits = t.wcache[tile];
+      } else {
       float wm = 0.f;
       for (int64_t q = pbeg + threadIdx.x; q < pend; q += BLOCK) {
         int64_t r = q;
@@ -565,9 +572,13 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
       }
       for (int o = 32; o > 0; o >>= 1) wm = fmaxf(wm, __shfl_xor(wm, o));
       if (__lane_id() == 0) atomicMax(wbits, __float_as_uint(wm));
+      }
     }
     __syncthreads();
-    const int shift = kFixed ? fixed_shift<T>(s, __uint_as_float(*wbits), D) : 0;
+    const float wbound = kFixed ? __uint_as_float(*wbits) : 0.f;
+    if (kFixed && t.wmode == 1 && threadIdx.x == 0) t.wcache[tile] = __float_as_uint(wbound);
+    const bool wcheck = kFixed && t.wmode == 2;
+    const int shift = kFixed ? fixed_shift<T>(s, wbound, D) : 0;
     // the current's coefficients, in the fixed-point box's units (2^shift)
     const T tjc[3] = {scale2(s.jc[0], shift), scale2(s.jc[1], shift), scale2(s.jc[2], shift)};
     const T tjz = scale2(s.jz, shift);
@@ -639,6 +650,7 @@ __global__ void __launch_bounds__(BLOCK) k_push_deposit_tiled(SpeciesArgs<T> s, 
           const int L = d == 0 ? geo.L0 : (d == 1 ? geo.L1 : geo.L2);
           inside = inside && (l >= -geo.S) && (l < L + geo.S);
         }
+        if (wcheck) inside = inside && !(fabsf(static_cast<float>(w)) > wbound);
       }
       const bool stray = have && !inside;
       const uint64_t out = __ballot(stray);
@@ -1069,6 +1081,11 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   // ones leave the tiles with few particles to the straggler kernel
   t.live = src ? live_tiles(c, sp) : dense_tiles(c, sp);
   const int32_t *few = src ? nullptr : sparse_tiles(c, sp);
+  // the fixed-point current's tile bounds: found by the first launch after
+  // the species' sort, taken from it by the later ones
+  const int slot = c.accfix ? sorted_slot(c, sp) : -1;
+  t.wcache = slot < 0 ? nullptr : c.wsp<uint32_t>(c.ws.wmax_tiles) + static_cast<size_t>(slot) * c.ntiles;
+  t.wmode = slot < 0 ? 0 : (c.wmax_known[slot] ? 2 : 1);
   t.ntiles = c.ntiles;
   t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
   t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
@@ -1101,6 +1118,7 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
       e = launch_tiled<T, D, M, RuntimeGeom, 256>(c, sa, f, t, st);
   }
   if (e != hipSuccess) return e;
+  if (slot >= 0) c.wmax_known[slot] = true;
   int64_t blocks = (sp.np + 255) / 256;
   if (blocks > 1024) blocks = 1024;
   if (src) {  // the removed particles behind every tile, then the sets swap

@@ -62,6 +62,8 @@ struct Workspace {
                              // left non-empty, in tile order, then their count
   size_t dense_tiles = 0;    // int32[kMaxSpecies][ntiles + 1]: of those, the ones with kSparseTile particles or more
   size_t sparse_tiles = 0;   // int32[kMaxSpecies][ntiles + 1]: and the others (3D; empty in 2D)
+  size_t wmax_tiles = 0;     // uint32[kMaxSpecies][ntiles]: per tile, the bits of its largest |w| (FP32) as
+                             // the first fused launch after the slot's last sort found it
   size_t partials = 0;    // double[kDiagSlots][kMaxSpecies * kDiagBlocks]
   size_t result = 0;      // double[16]
   size_t rho = 0;         // double[ncells]
@@ -106,6 +108,9 @@ struct pic_ctx {
   int32_t *live_host = nullptr;  // pinned, kMaxSpecies entries (allocated on first use)
   hipEvent_t live_event[pic::kMaxSpecies] = {};
   bool live_pending[pic::kMaxSpecies] = {};
+  // The fixed-point current's per-tile weight bound: true once a fused launch
+  // has stored it for slot i's current sort (cleared by every sort of the slot)
+  mutable bool wmax_known[pic::kMaxSpecies] = {};  // set by the launch (which sees the context as const)
   bool has_laser = false;
   pic_laser laser{};
   double laser_j0 = 0.0;  // sheet amplitude radiating laser.e0 on the lattice
@@ -185,6 +190,8 @@ const int32_t *live_tiles(const pic_ctx &c, const pic_species &sp);
 constexpr int kSparseTile = 32;
 const int32_t *dense_tiles(const pic_ctx &c, const pic_species &sp);
 const int32_t *sparse_tiles(const pic_ctx &c, const pic_species &sp);
+// The workspace slot of the species' last sort (as live_tiles finds it), or -1.
+int sorted_slot(const pic_ctx &c, const pic_species &sp);
 
 int64_t sort_scan_blocks(int64_t nbuckets);
 int64_t sort_scan_capacity();

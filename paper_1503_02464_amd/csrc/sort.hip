@@ -687,6 +687,7 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
     }
   }
   int32_t *start = c.wsp<int32_t>(c.ws.bucket_start) + static_cast<size_t>(slot) * (nb + 1);
+  c.wmax_known[slot] = false;  // the tiles change: the next fused launch finds their weight bounds again
   int32_t *live = c.wsp<int32_t>(c.ws.live_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
   int32_t *dense = c.wsp<int32_t>(c.ws.dense_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
   int32_t *few = c.wsp<int32_t>(c.ws.sparse_tiles) + static_cast<size_t>(slot) * (c.ntiles + 1);
@@ -768,12 +769,16 @@ hipError_t launch_sort(pic_ctx &c, pic_species &sp, hipStream_t s, const int32_t
   return hipSuccess;
 }
 
+int sorted_slot(const pic_ctx &c, const pic_species &sp) {
+  for (size_t i = 0; i < c.sorted_runs.size(); ++i)
+    if (c.sorted_runs[i].first == sp.tile_start && c.sorted_runs[i].second == sp.np) return static_cast<int>(i);
+  return -1;
+}
+
 namespace {
 const int32_t *tile_list(const pic_ctx &c, const pic_species &sp, size_t base) {
-  for (size_t i = 0; i < c.sorted_runs.size(); ++i)
-    if (c.sorted_runs[i].first == sp.tile_start && c.sorted_runs[i].second == sp.np)
-      return c.wsp<int32_t>(base) + i * (c.ntiles + 1);
-  return nullptr;
+  const int i = sorted_slot(c, sp);
+  return i < 0 ? nullptr : c.wsp<int32_t>(base) + static_cast<size_t>(i) * (c.ntiles + 1);
 }
 }  // namespace
 

@@ -7,6 +7,7 @@ particles to stage (stepped by the straggler kernel).  FP64 to 1e-12; FP32
 one step from an FP32-representable state (gpu_helpers.TOL)."""
 import numpy as np
 import pytest
+import torch
 
 import oracle as O
 from gpu_helpers import compare_fields, compare_species, grid, make_sim, state, unique_weights
@@ -302,4 +303,33 @@ def test_sparse_tiles(prec):
     s.check()
     compare_species(g, prec, s.get_species(h), ref_sp, "sparse tiles")
     compare_fields(prec, s.get_fields(), ref_f, what="sparse tiles")
+    s.close()
+
+
+@pytest.mark.parametrize("dims", [2, 3])
+def test_weights_raised_after_the_tile_bounds_were_taken(dims):
+    """FP32 state: the first fused launch after a sort finds each tile's
+    largest weight (the scale of its fixed-point current) and the later ones
+    reuse it.  Weights raised fourfold between steps, without a sort, must
+    not overflow that scale: those particles take the HBM path, and one step
+    from the changed state matches the oracle."""
+    g = grid(dims, (32, 16) if dims == 2 else (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    sp, f = drifting(g, "fp32", 4, (0.3, -0.2, 0.1), seed=650 + dims)
+    tile = (8, 4, 1) if dims == 2 else (8, 4, 4)
+    s = make_sim(g, "fp32", tile, slack=1, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    s.step(2)  # the first step sorts and takes the bounds, the second reuses them
+    w = h.current()["w"]
+    heavy = torch.arange(0, h.np, 7, device=w.device)
+    w[heavy] *= 4.0
+    ref_sp, ref_f = gpu_state(s, h)
+    ref_sp["q"], ref_sp["m"] = sp["q"], sp["m"]
+    ref_f["J"] = np.zeros_like(ref_f["J"])
+    s.step(1)
+    s.check()
+    assert s.straggler_count() >= heavy.numel() * 9 // 10, s.straggler_count()
+    assert O.step(g, ref_f, [ref_sp]) == 0
+    compare_species(g, "fp32", s.get_species(h), ref_sp, "raised weights")
+    compare_fields("fp32", s.get_fields(), ref_f, what="raised weights")
     s.close()
