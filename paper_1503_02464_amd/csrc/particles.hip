@@ -1119,8 +1119,10 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   }
   if (e != hipSuccess) return e;
   if (slot >= 0) c.wmax_known[slot] = true;
+  // up to 4096 workgroups of four wavefronts: the straggler kernel gives each
+  // sparse tile a wavefront, and a box of many such tiles keeps them in flight
   int64_t blocks = (sp.np + 255) / 256;
-  if (blocks > 1024) blocks = 1024;
+  if (blocks > 4096) blocks = 4096;
   if (src) {  // the removed particles behind every tile, then the sets swap
     hipLaunchKernelGGL((k_fold_tail<T, D>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, sa,
                        sp.tile_start, c.ntiles);
