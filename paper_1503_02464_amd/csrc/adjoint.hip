@@ -597,7 +597,7 @@ hipError_t particle_adjoint_impl(const pic_ctx &c, const pic_species &sp, const 
       t.gj_lo[d] = c.gj_lo[d];
     }
     t.slack = c.p.slack;
-    t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
+    t.stray_count = c.wsp<int32_t>(c.ws.stray_count) + 32;  // behind the fused launches' two banks
     t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
     const auto kern = k_particle_adjoint_tiled<T, D, M>;
     hipError_t e = launch_fill_zero(t.stray_count, 1, 4, st);

@@ -264,7 +264,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.sort_key = take(mp * 4);
   w.sort_rank = take(mp * 4);
   w.sort_src = take(mp * 4);
-  w.stray_count = take(16 * 4);
+  w.stray_count = take(48 * 4);
   w.stray_list = take(mp * 4);
   // sort buckets: (tile, level) pairs plus one for particles removed at open faces
   const int64_t nbuckets = c->ntiles * c->levels + 1;
@@ -331,6 +331,7 @@ pic_status pic_set_workspace(pic_ctx *c, void *ptr, size_t bytes) {
   // the previous workspace
   c->sorted_runs.clear();
   for (int i = 0; i < pic::kMaxSpecies; ++i) c->wmax_known[i] = false;
+  c->stray_clean = false;  // the next fused launch clears its counters itself
   hipError_t e = hipMemset(c->wsptr + c->ws.flags, 0, 64 * sizeof(int32_t));
   if (e != hipSuccess) return hip_fail(c, e, "clearing workspace flags");
   return PIC_OK;
@@ -651,7 +652,9 @@ pic_status pic_straggler_count(pic_ctx *c, int64_t *count, void *stream) {
   if (pic_status s = check_ws(c)) return s;
   hipStream_t s = static_cast<hipStream_t>(stream);
   int32_t n = 0;
-  hipError_t e = hipMemcpyAsync(&n, c->wsptr + c->ws.stray_count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  // the last fused launch's bank
+  const size_t at = c->ws.stray_count + static_cast<size_t>(c->stray_last) * 16 * sizeof(int32_t);
+  hipError_t e = hipMemcpyAsync(&n, c->wsptr + at, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(c, e, "straggler count");
   *count = n;

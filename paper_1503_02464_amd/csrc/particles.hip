@@ -872,7 +872,10 @@ template <typename T, int D, int M>
 __global__ void __launch_bounds__(256) k_stragglers(SpeciesArgs<T> s, GridArgs g, GlobalFields<T> gf,
                                                     GlobalCurrent<T> gj, const int32_t *count, const int32_t *list,
                                                     const int32_t *few, const int32_t *tile_start, int64_t ntiles,
-                                                    int32_t *flags) {
+                                                    int32_t *flags, int32_t *clear_next) {
+  // the other counter bank, which the next fused launch takes (this launch
+  // does not read it)
+  if (clear_next && blockIdx.x == 0 && threadIdx.x < 9) clear_next[threadIdx.x] = 0;
   const int64_t n = *count;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     push_hbm<T, D, M>(s, g, gf, gj, list[k], flags);
@@ -1087,11 +1090,17 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   t.wcache = slot < 0 ? nullptr : c.wsp<uint32_t>(c.ws.wmax_tiles) + static_cast<size_t>(slot) * c.ntiles;
   t.wmode = slot < 0 ? 0 : (c.wmax_known[slot] ? 2 : 1);
   t.ntiles = c.ntiles;
-  t.stray_count = c.wsp<int32_t>(c.ws.stray_count);
+  // the straggler count and the 8 queues, in this launch's bank: zero if the
+  // previous launch's straggler kernel cleared it, else cleared here
+  const int bank = c.stray_bank;
+  int32_t *banks = c.wsp<int32_t>(c.ws.stray_count);
+  t.stray_count = banks + 16 * bank;
   t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
   t.queue = t.stray_count + 1;
   t.cross_cap = c.cross_cap;
-  hipError_t e = launch_fill_zero(t.stray_count, 9, 4, st);  // the straggler count and the 8 queues
+  hipError_t e = hipSuccess;
+  if (!c.stray_clean) e = launch_fill_zero(t.stray_count, 9, 4, st);
+  c.stray_clean = false;  // until this launch's straggler kernel has gone out
   if (e != hipSuccess) return e;
   const int *L = c.p.tile;
   const int sl = c.p.slack;
@@ -1132,8 +1141,14 @@ hipError_t tiled_impl(const pic_ctx &c, pic_species &sp, const pic_fields &f, hi
   }
   hipLaunchKernelGGL((k_stragglers<T, D, M>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
                      species_args<T>(c, sp), grid_args(c), global_fields<T>(c, f), global_current<T>(c, f),
-                     t.stray_count, t.stray_list, few, sp.tile_start, c.ntiles, c.wsp<int32_t>(c.ws.flags));
-  return hipGetLastError();
+                     t.stray_count, t.stray_list, few, sp.tile_start, c.ntiles, c.wsp<int32_t>(c.ws.flags),
+                     banks + 16 * (1 - bank));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  c.stray_last = bank;
+  c.stray_bank = 1 - bank;
+  c.stray_clean = true;
+  return hipSuccess;
 }
 
 template <template <typename, int, int> class F, typename... A>

@@ -52,7 +52,8 @@ struct Workspace {
   size_t sort_key = 0;    // int32[max_particles]
   size_t sort_rank = 0;   // int32[max_particles]
   size_t sort_src = 0;    // int32[max_particles]: the particle each sorted slot takes
-  size_t stray_count = 0; // int32[16]: [0] particles the tiled kernel left outside their LDS box, [1..8] its tile queues
+  size_t stray_count = 0; // int32[2][16] + int32[16]: two banks of the tiled kernel's counters ([0] the particles
+                          // it left outside their LDS box, [1..8] its tile queues), then the adjoint's count
   size_t stray_list = 0;  // int32[max_particles]: their indices
   size_t stay_count = 0;    // int32[ntiles * levels]: per (tile, level) bucket, particles that stayed in the tile
   size_t arrive_count = 0;  // int32[ntiles * levels]: per bucket, the others
@@ -111,6 +112,12 @@ struct pic_ctx {
   // The fixed-point current's per-tile weight bound: true once a fused launch
   // has stored it for slot i's current sort (cleared by every sort of the slot)
   mutable bool wmax_known[pic::kMaxSpecies] = {};  // set by the launch (which sees the context as const)
+  // The fused launches alternate between the two counter banks: each launch's
+  // straggler kernel clears the bank the next launch takes, so a launch needs
+  // no clear of its own unless the chain broke (a failed call, a new workspace).
+  mutable int stray_bank = 0;       // the bank the next fused launch takes
+  mutable int stray_last = 0;       // the bank of the last fused launch
+  mutable bool stray_clean = false; // the next bank is known to be zero
   bool has_laser = false;
   pic_laser laser{};
   double laser_j0 = 0.0;  // sheet amplitude radiating laser.e0 on the lattice
