@@ -396,7 +396,7 @@ pic_status pic_check(pic_ctx *ctx, void *stream);
 pic_status pic_set_timing(pic_ctx *ctx, int32_t on);
 pic_status pic_get_timing(pic_ctx *ctx, double *ms, int64_t *launches, int32_t nphase);
 
-/* Number of particles the last fused launch handed to the HBM path because
+/* Number of particles the last fused launch (or tiled adjoint call) handed to the HBM path because
  * their cell was more than `slack` cells outside their tile (synchronising).
  * A large value means the species should be sorted more often. */
 pic_status pic_straggler_count(pic_ctx *ctx, int64_t *count, void *stream);

@@ -597,9 +597,13 @@ hipError_t particle_adjoint_impl(const pic_ctx &c, const pic_species &sp, const 
       t.gj_lo[d] = c.gj_lo[d];
     }
     t.slack = c.p.slack;
-    t.stray_count = c.wsp<int32_t>(c.ws.stray_count) + 32;  // behind the fused launches' two banks
+    // the count goes to the bank the next fused launch takes, which then
+    // clears that bank itself; the straggler count reads this call's
+    t.stray_count = c.wsp<int32_t>(c.ws.stray_count) + 16 * c.stray_bank;
     t.stray_list = c.wsp<int32_t>(c.ws.stray_list);
     const auto kern = k_particle_adjoint_tiled<T, D, M>;
+    c.stray_clean = false;
+    c.stray_last = c.stray_bank;
     hipError_t e = launch_fill_zero(t.stray_count, 1, 4, st);
     if (e == hipSuccess && lds > 65536)
       e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -264,7 +264,7 @@ pic_status pic_init(const pic_params *p, pic_ctx **out) {
   w.sort_key = take(mp * 4);
   w.sort_rank = take(mp * 4);
   w.sort_src = take(mp * 4);
-  w.stray_count = take(48 * 4);
+  w.stray_count = take(32 * 4);
   w.stray_list = take(mp * 4);
   // sort buckets: (tile, level) pairs plus one for particles removed at open faces
   const int64_t nbuckets = c->ntiles * c->levels + 1;

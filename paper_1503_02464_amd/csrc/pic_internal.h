@@ -52,8 +52,8 @@ struct Workspace {
   size_t sort_key = 0;    // int32[max_particles]
   size_t sort_rank = 0;   // int32[max_particles]
   size_t sort_src = 0;    // int32[max_particles]: the particle each sorted slot takes
-  size_t stray_count = 0; // int32[2][16] + int32[16]: two banks of the tiled kernel's counters ([0] the particles
-                          // it left outside their LDS box, [1..8] its tile queues), then the adjoint's count
+  size_t stray_count = 0; // int32[2][16]: two banks of the tiled kernel's counters ([0] the particles it left
+                          // outside their LDS box, [1..8] its tile queues)
   size_t stray_list = 0;  // int32[max_particles]: their indices
   size_t stay_count = 0;    // int32[ntiles * levels]: per (tile, level) bucket, particles that stayed in the tile
   size_t arrive_count = 0;  // int32[ntiles * levels]: per bucket, the others

@@ -32,6 +32,32 @@ def gpu_state(s, h):
     return sp, f
 
 
+def test_straggler_count_per_launch():
+    """The fused launches alternate two banks of counters, each cleared by the
+    launch before it: the launch after a sort reports no straggler although
+    the launch before it had many, and every launch's particles and fields
+    stay the oracle's (FP64, 3D, slack 0)."""
+    g = grid(3, (16, 16, 8), dx=0.05, cfl=0.7, order=2)
+    sp, f = drifting(g, "fp64", 2, (2.0, -1.0, 0.5), seed=640)
+    s = make_sim(g, "fp64", (8, 4, 4), slack=0, sort_every=1 << 30, max_particles=sp["w"].shape[0])
+    s.set_fields(f["E"], f["B"])
+    h = s.add_species(sp)
+    ref_sp, ref_f = O.copy_species(sp), {k: v.copy() for k, v in f.items()}
+    counts = []
+    for n in range(4):
+        if n == 2:
+            s.sort(h)
+        s.step(1)
+        counts.append(s.straggler_count())
+        assert O.step(g, ref_f, [ref_sp]) == 0
+    s.check()
+    assert counts[0] == 0 and counts[2] == 0, counts
+    assert counts[1] > sp["w"].shape[0] // 20 and counts[3] > sp["w"].shape[0] // 20, counts
+    compare_species(g, "fp64", s.get_species(h), ref_sp, "straggler banks")
+    compare_fields("fp64", s.get_fields(), ref_f, what="straggler banks")
+    s.close()
+
+
 @pytest.mark.parametrize("prec,dims", [(p, d) for p in ("fp64", "fp32") for d in (2, 3)])
 def test_stragglers(prec, dims):
     """Slack 0 and no re-sort: after the first step every particle that left its
