@@ -261,7 +261,12 @@ pic_status pic_sort(pic_ctx *ctx, pic_species *sp, void *stream);
  * (and, with open_x, removal of the particles that left); then the Yee
  * update.  In 3D, after a sort the push reads each particle through the
  * sort's slots and writes it into the second array set, which then becomes
- * the current one: the same swap and tile_start as pic_sort gives. */
+ * the current one: the same swap and tile_start as pic_sort gives.
+ * The context keeps state between calls (sorted runs, cached tile weight
+ * bounds, which of two counter banks in the workspace the next fused launch
+ * takes, its straggler kernel clearing the other): calls on one context run
+ * in stream order, one at a time, and a call is not captured into a graph
+ * for replay. */
 pic_status pic_step(pic_ctx *ctx, pic_species *sp, int32_t nspecies, pic_fields *f, int32_t nsteps, void *stream);
 
 /* FP64 diagnostics of the current state, accumulated in double on the device,
